@@ -1,0 +1,164 @@
+#!/usr/bin/env python
+"""Benchmark of the MERF deferred renderer on one MI355X.
+
+Workload: the full-size plain FP32 scene (512^3 sparse grid of 8^3 blocks at
+~5% occupancy, three 2048^2 uint8 planes with 8 channels, 3-level occupancy
+pyramid, content to ||x||_inf = 100 before contraction) rendered from one
+1920x1080 camera inside the unit cube.  A step is one merf_render call of that
+frame (ray generation, contraction, skipping, gathers, compositing and the
+deferred MLP -- the whole hot path, one kernel launch).  Inputs are resident
+in device memory before timing starts.
+
+Prints ONE JSON line.  Besides throughput it reports:
+  roofline      algorithmic gather bytes per launch / average kernel time
+                (HIP events on the launch stream), against HBM peak;
+  latency_ms    p50 / p99 of per-frame GPU time;
+  cpu_baseline  the FP64 oracle on a bounded row sample of the same frame.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "rays/sec (Mrays/s) at 1080p, % HBM roofline; p50/p99 frame latency served vs plain"
+# algorithmic bytes (density first): per evaluated sample 20 density codes +
+# 4 B brick index; per sample with alpha != 0 another 20 x 7 appearance codes;
+# 1 B per occupancy lookup; 16 B of output per ray.
+B_EVAL, B_CONTRIB, B_OCC, B_RAY = 24, 140, 1, 16
+KERNEL_SOURCES = ["paper_2302_12249_amd/csrc/merf_render.hip", "paper_2302_12249_amd/csrc/merf_device.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_full_1080p_traffic.json")
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
+    were taken on the current kernel source; otherwise None."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(scene, cams, seconds: float):
+    import oracle
+    os_ = oracle.OracleScene(scene)
+    W, H = int(cams.size[0, 0]), int(cams.size[0, 1])
+    t0 = time.perf_counter()
+    pilot_stride = 135                      # 8 rows
+    oracle.render(os_, cams, rows_stride=pilot_stride, row_offset=0, fragile=False, stats=False)
+    t_pilot = time.perf_counter() - t0
+    per_row = t_pilot / len(range(0, H, pilot_stride))
+    rows = max(8, min(H, int(seconds / max(per_row, 1e-9))))
+    stride = max(1, H // rows)
+    t0 = time.perf_counter()
+    out, _ = oracle.render(os_, cams, rows_stride=stride, row_offset=stride // 2, fragile=False, stats=False)
+    dt = time.perf_counter() - t0
+    n = out.shape[0]
+    return {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"every {stride}th row of the {W}x{H} frame ({n} rays, {dt:.1f} s, FP64 C, OpenMP)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this renderer runs on one GPU; --gpus {args.gpus} is not supported "
+              "(every pixel is independent, so more GPUs would split cameras or tiles; not built).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    from paper_2302_12249_amd import merf
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    scene = synth.preset_scene("full")
+    cams = synth.full_camera()
+    rays = cams.num_pixels()
+    r = merf.Renderer(scene)
+    stream = torch.cuda.current_stream()
+    out = torch.empty((rays, 4), dtype=torch.float32, device="cuda")
+
+    # untimed: counters of the work one frame does
+    st = torch.zeros(8, dtype=torch.int64, device="cuda")
+    r.render(cams, out=out, stats=st)
+    torch.cuda.synchronize()
+    cnt = st.cpu().numpy()
+    n_rays, occ_lookups, visited, evaluated, contributing = [int(v) for v in cnt[:5]]
+    alg_bytes = evaluated * B_EVAL + contributing * B_CONTRIB + occ_lookups * B_OCC + n_rays * B_RAY
+
+    for _ in range(args.warmup):
+        r.render(cams, out=out)
+    torch.cuda.synchronize()
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        r.render(cams, out=out)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = np.array([a.elapsed_time(b) for a, b in ev])          # ms, GPU time per frame
+    r.close()
+
+    ms_per_step = wall * 1e3 / args.steps
+    kernel_ms = float(per.mean())
+    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    traffic = measured_traffic()
+    res = {
+        "metric": METRIC,
+        "value": rays / (ms_per_step * 1e-3) / 1e6,
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "full-size plain FP32: 512^3 sparse grid of 8^3 blocks (~5% occupied), three "
+                               "2048^2 uint8 planes x 8 channels, 3-level occupancy (16^3/64^3/128^3), "
+                               "one 1920x1080 view from inside the unit cube",
+                   "scene_seed": scene.seed, "camera_seed": 22, "rays_per_step": rays, "step": scene.step},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic},
+        "kernel_ms": kernel_ms,
+        "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99))},
+        "per_ray": {"evaluated": evaluated / n_rays, "contributing": contributing / n_rays,
+                    "visited": visited / n_rays, "occ_lookups": occ_lookups / n_rays},
+        "alg_bytes_per_launch": alg_bytes,
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(scene, cams, args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

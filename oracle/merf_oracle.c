@@ -424,13 +424,17 @@ int or_render_ray(const or_scene *s, const or_params *P, const double o[3], cons
     const double step = P->step;
 
     if (P->want_fragile) {
-        /* Grazing: two region-candidate parameters almost equal, at a point that
-         * is occupied, may give an extra or a missing tiny segment in FP32. */
+        /* Grazing: two region-candidate parameters almost equal, at a point on
+         * or outside the unit cube (inside it the seams do not change the
+         * region) that is occupied, may give an extra or a missing tiny
+         * segment in FP32. */
         double cand[OR_MAX_CAND];
         int nc = or_candidates(o, d, cand);
         for (int i = 0; i + 1 < nc; ++i) {
             if (cand[i + 1] - cand[i] <= 1e-6 * fmax(1.0, cand[i])) {
                 double x[3] = {o[0] + cand[i] * d[0], o[1] + cand[i] * d[1], o[2] + cand[i] * d[2]};
+                double r = fmax(fabs(x[0]), fmax(fabs(x[1]), fabs(x[2])));
+                if (r < 1.0 - 1e-6) continue;
                 double y[3];
                 or_contract(x, y);
                 if (or_occupied(s, y)) fragile = 1;

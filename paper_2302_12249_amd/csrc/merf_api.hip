@@ -1,0 +1,347 @@
+// merf_api.hip -- host side of the C ABI declared in include/merf.h:
+// argument validation, device residency and HBM budget of baked scenes,
+// launch of the render kernels, thread-local error reporting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "merf.h"
+#include "merf_device.h"
+
+using namespace merf;
+
+struct merf_scene {
+    uint32_t magic;
+    void *dev_base;
+    size_t dev_bytes;
+    DevScene ds;
+    int32_t nbricks;
+};
+
+namespace {
+
+constexpr uint32_t kMagic = 0x4d455246u;  // "MERF"
+
+thread_local std::string g_error;
+std::mutex g_mutex;
+std::unordered_set<merf_scene *> g_live;
+size_t g_budget = SIZE_MAX;
+size_t g_in_use = 0;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(MERF_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+bool live(merf_scene *s) {
+    std::lock_guard<std::mutex> lk(g_mutex);
+    return s && g_live.count(s) && s->magic == kMagic;
+}
+
+int validate_desc(const merf_scene_desc *d) {
+    if (!d) return fail(MERF_E_INVALID, "scene descriptor is NULL");
+    if (d->struct_size != sizeof(merf_scene_desc))
+        return fail(MERF_E_INVALID, "struct_size %u != sizeof(merf_scene_desc) %zu", d->struct_size,
+                    sizeof(merf_scene_desc));
+    if (d->block_size != kBlock) return fail(MERF_E_INVALID, "block_size must be %d (got %d)", kBlock, d->block_size);
+    if (d->channels != kChannels) return fail(MERF_E_INVALID, "channels must be %d (got %d)", kChannels, d->channels);
+    if (d->grid_res < 2 * kBlock || d->grid_res % kBlock != 0 || d->grid_res > 4096)
+        return fail(MERF_E_INVALID, "grid_res %d must be a multiple of 8 in [16, 4096]", d->grid_res);
+    if (d->plane_res < 2 || d->plane_res > 16384)
+        return fail(MERF_E_INVALID, "plane_res %d must be in [2, 16384]", d->plane_res);
+    const int64_t nbl = d->grid_res / kBlock;
+    if (d->num_blocks < 0 || d->num_blocks > nbl * nbl * nbl)
+        return fail(MERF_E_INVALID, "num_blocks %d out of range", d->num_blocks);
+    if (!d->block_index) return fail(MERF_E_INVALID, "block_index is NULL");
+    if (d->num_blocks > 0 && !d->blocks) return fail(MERF_E_INVALID, "blocks is NULL");
+    if (!d->planes) return fail(MERF_E_INVALID, "planes is NULL");
+    if (d->occ_levels < 1 || d->occ_levels > MERF_MAX_OCC_LEVELS)
+        return fail(MERF_E_INVALID, "occ_levels %d must be in [1, %d]", d->occ_levels, MERF_MAX_OCC_LEVELS);
+    for (int l = 0; l < d->occ_levels; ++l) {
+        if (d->occ_res[l] < 1 || d->occ_res[l] > 2048)
+            return fail(MERF_E_INVALID, "occ_res[%d] = %d must be in [1, 2048]", l, d->occ_res[l]);
+        if (!d->occ[l]) return fail(MERF_E_INVALID, "occ[%d] is NULL", l);
+    }
+    if (!(d->m_density > 0.0f) || !(d->m_feature > 0.0f) || !std::isfinite(d->m_density) ||
+        !std::isfinite(d->m_feature))
+        return fail(MERF_E_INVALID, "m_density / m_feature must be positive and finite");
+    if (d->mlp_in != kMlpIn || d->mlp_hidden != kMlpHidden)
+        return fail(MERF_E_INVALID, "MLP must be %d -> %d -> %d -> 3 (got in=%d hidden=%d)", kMlpIn, kMlpHidden,
+                    kMlpHidden, d->mlp_in, d->mlp_hidden);
+    if (!d->mlp_params) return fail(MERF_E_INVALID, "mlp_params is NULL");
+    const int64_t nidx = nbl * nbl * nbl;
+    std::vector<uint8_t> seen((size_t)std::max(d->num_blocks, 1), 0);
+    for (int64_t i = 0; i < nidx; ++i) {
+        int32_t b = d->block_index[i];
+        if (b < -1 || b >= d->num_blocks)
+            return fail(MERF_E_INVALID, "block_index[%lld] = %d out of [-1, %d)", (long long)i, b, d->num_blocks);
+        if (b >= 0) {
+            if (seen[(size_t)b]) return fail(MERF_E_INVALID, "block slot %d referenced twice", b);
+            seen[(size_t)b] = 1;
+        }
+    }
+    return MERF_OK;
+}
+
+// Bricks with a one-voxel apron: brick (bx, by, bz) holds voxels 8b .. 8b+8 of
+// each axis.  A brick is needed when any of the 8 blocks it touches is stored.
+void build_bricks(const merf_scene_desc *d, std::vector<int32_t> &bidx, std::vector<uint8_t> &bricks) {
+    const int L = d->grid_res, nbl = L / kBlock;
+    auto block_at = [&](int bx, int by, int bz) -> int32_t {
+        if (bx >= nbl || by >= nbl || bz >= nbl) return -1;
+        return d->block_index[((size_t)bz * nbl + by) * nbl + bx];
+    };
+    bidx.assign((size_t)nbl * nbl * nbl, -1);
+    int32_t n = 0;
+    for (int bz = 0; bz < nbl; ++bz)
+        for (int by = 0; by < nbl; ++by)
+            for (int bx = 0; bx < nbl; ++bx) {
+                bool need = false;
+                for (int dz = 0; dz < 2 && !need; ++dz)
+                    for (int dy = 0; dy < 2 && !need; ++dy)
+                        for (int dx = 0; dx < 2 && !need; ++dx) need = block_at(bx + dx, by + dy, bz + dz) >= 0;
+                if (need) bidx[((size_t)bz * nbl + by) * nbl + bx] = n++;
+            }
+    bricks.assign((size_t)n * kBrickBytes, 0);
+    for (int bz = 0; bz < nbl; ++bz)
+        for (int by = 0; by < nbl; ++by)
+            for (int bx = 0; bx < nbl; ++bx) {
+                int32_t slot = bidx[((size_t)bz * nbl + by) * nbl + bx];
+                if (slot < 0) continue;
+                uint8_t *dst = bricks.data() + (size_t)slot * kBrickBytes;
+                for (int lz = 0; lz < kBrick; ++lz)
+                    for (int ly = 0; ly < kBrick; ++ly)
+                        for (int lx = 0; lx < kBrick; ++lx) {
+                            int x = bx * kBlock + lx, y = by * kBlock + ly, z = bz * kBlock + lz;
+                            if (x >= L || y >= L || z >= L) continue;
+                            int32_t src = block_at(x / kBlock, y / kBlock, z / kBlock);
+                            if (src < 0) continue;
+                            const uint8_t *s = d->blocks + ((((size_t)src * kBlock + (z % kBlock)) * kBlock +
+                                                             (y % kBlock)) * kBlock + (x % kBlock)) * kChannels;
+                            std::memcpy(dst + (((size_t)lz * kBrick + ly) * kBrick + lx) * kChannels, s, kChannels);
+                        }
+            }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *merf_last_error(void) { return g_error.c_str(); }
+
+int merf_set_hbm_budget(size_t bytes) {
+    std::lock_guard<std::mutex> lk(g_mutex);
+    g_budget = bytes;
+    return MERF_OK;
+}
+
+size_t merf_hbm_in_use(void) {
+    std::lock_guard<std::mutex> lk(g_mutex);
+    return g_in_use;
+}
+
+size_t merf_scene_bytes(merf_scene_t s) { return live(s) ? s->dev_bytes : 0; }
+
+int merf_scene_upload(const merf_scene_desc *desc, merf_scene_t *out) {
+    g_error.clear();
+    if (!out) return fail(MERF_E_INVALID, "output handle pointer is NULL");
+    *out = nullptr;
+    int rc = validate_desc(desc);
+    if (rc) return rc;
+
+    std::vector<int32_t> bidx;
+    std::vector<uint8_t> bricks;
+    build_bricks(desc, bidx, bricks);
+    const int L = desc->grid_res, R = desc->plane_res, nbl = L / kBlock;
+
+    // one device allocation, sub-allocated at 256-byte boundaries
+    size_t off = 0;
+    const size_t o_bidx = off; off = align_up(off + bidx.size() * sizeof(int32_t), 256);
+    const size_t o_bricks = off; off = align_up(off + std::max<size_t>(bricks.size(), 8), 256);
+    const size_t o_planes = off; off = align_up(off + (size_t)3 * R * R * kChannels, 256);
+    size_t o_occ[kMaxLevels] = {0, 0, 0, 0};
+    for (int l = 0; l < desc->occ_levels; ++l) {
+        size_t r = (size_t)desc->occ_res[l];
+        o_occ[l] = off;
+        off = align_up(off + r * r * r, 256);
+    }
+    const size_t o_mlp = off; off = align_up(off + kMlpParams * sizeof(float), 256);
+    const size_t total = off;
+
+    {
+        std::lock_guard<std::mutex> lk(g_mutex);
+        if (g_in_use + total > g_budget)
+            return fail(MERF_E_OOM, "scene needs %zu device bytes; %zu in use, budget %zu", total, g_in_use, g_budget);
+        g_in_use += total;    // reserve; released below on failure
+    }
+    auto release = [&]() {
+        std::lock_guard<std::mutex> lk(g_mutex);
+        g_in_use -= total;
+    };
+
+    void *base = nullptr;
+    hipError_t e = hipMalloc(&base, total);
+    if (e != hipSuccess || !base) {
+        (void)hipGetLastError();
+        release();
+        return fail(MERF_E_OOM, "hipMalloc(%zu) failed: %s", total, hipGetErrorString(e));
+    }
+    auto dev = [&](size_t o) { return static_cast<uint8_t *>(base) + o; };
+    struct Copy { size_t off; const void *src; size_t n; };
+    std::vector<Copy> copies = {
+        {o_bidx, bidx.data(), bidx.size() * sizeof(int32_t)},
+        {o_bricks, bricks.data(), bricks.size()},
+        {o_planes, desc->planes, (size_t)3 * R * R * kChannels},
+        {o_mlp, desc->mlp_params, kMlpParams * sizeof(float)},
+    };
+    for (int l = 0; l < desc->occ_levels; ++l) {
+        size_t r = (size_t)desc->occ_res[l];
+        copies.push_back({o_occ[l], desc->occ[l], r * r * r});
+    }
+    for (const Copy &c : copies) {
+        if (c.n == 0) continue;
+        e = hipMemcpy(dev(c.off), c.src, c.n, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(base);
+            release();
+            return hip_fail(e, "hipMemcpy (scene upload)");
+        }
+    }
+
+    merf_scene *s = new merf_scene();
+    s->magic = kMagic;
+    s->dev_base = base;
+    s->dev_bytes = total;
+    s->nbricks = (int32_t)(bricks.size() / kBrickBytes);
+    DevScene &ds = s->ds;
+    ds.brick_index = reinterpret_cast<const int32_t *>(dev(o_bidx));
+    ds.bricks = dev(o_bricks);
+    ds.planes = dev(o_planes);
+    for (int l = 0; l < kMaxLevels; ++l) {
+        ds.occ[l] = l < desc->occ_levels ? dev(o_occ[l]) : nullptr;
+        ds.occ_res[l] = l < desc->occ_levels ? desc->occ_res[l] : 1;
+    }
+    ds.mlp = reinterpret_cast<const float *>(dev(o_mlp));
+    ds.L = L;
+    ds.R = R;
+    ds.nbl = nbl;
+    ds.occ_levels = desc->occ_levels;
+    ds.m_density = desc->m_density;
+    ds.m_feature = desc->m_feature;
+    {
+        std::lock_guard<std::mutex> lk(g_mutex);
+        g_live.insert(s);
+    }
+    *out = s;
+    return MERF_OK;
+}
+
+int merf_free(merf_scene_t s) {
+    g_error.clear();
+    {
+        std::lock_guard<std::mutex> lk(g_mutex);
+        if (!s || !g_live.count(s)) return fail(MERF_E_INVALID, "merf_free: unknown or already freed scene handle");
+        g_live.erase(s);
+    }
+    hipError_t e1 = hipDeviceSynchronize();
+    hipError_t e2 = hipFree(s->dev_base);
+    {
+        std::lock_guard<std::mutex> lk(g_mutex);
+        g_in_use -= s->dev_bytes;
+    }
+    s->magic = 0;
+    delete s;
+    if (e1 != hipSuccess) return hip_fail(e1, "hipDeviceSynchronize (merf_free)");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipFree (merf_free)");
+    return MERF_OK;
+}
+
+int merf_render(merf_scene_t s, const merf_camera *cams, int32_t n_cams, const merf_render_params *p,
+                float *out_rgba_dev, void *hip_stream) {
+    g_error.clear();
+    if (!live(s)) return fail(MERF_E_INVALID, "merf_render: invalid scene handle");
+    if (!p) return fail(MERF_E_INVALID, "merf_render: params is NULL");
+    if (p->struct_size != sizeof(merf_render_params))
+        return fail(MERF_E_INVALID, "params struct_size %u != %zu", p->struct_size, sizeof(merf_render_params));
+    if (n_cams < 0) return fail(MERF_E_INVALID, "n_cams %d < 0", n_cams);
+    if (n_cams == 0) return MERF_OK;
+    if (!cams) return fail(MERF_E_INVALID, "cams is NULL");
+    if (!out_rgba_dev) return fail(MERF_E_INVALID, "output buffer is NULL");
+    const float step = p->step > 0.0f ? p->step : 4.0f / (float)s->ds.R;
+    if (!std::isfinite(step) || step < 1e-6f) return fail(MERF_E_INVALID, "step %g out of range", (double)p->step);
+    if (!(p->t_min >= 0.0f && p->t_min < 1.0f)) return fail(MERF_E_INVALID, "t_min %g not in [0, 1)", (double)p->t_min);
+    if (p->delta_mode != 0 && p->delta_mode != 1) return fail(MERF_E_INVALID, "delta_mode %d", p->delta_mode);
+    if (p->mlp_prec != 0) return fail(MERF_E_INVALID, "mlp_prec %d not supported", p->mlp_prec);
+    if (p->feat_prec != 0) return fail(MERF_E_INVALID, "feat_prec %d not supported", p->feat_prec);
+    for (int i = 0; i < n_cams; ++i) {
+        const merf_camera &c = cams[i];
+        if (c.width < 1 || c.height < 1 || c.width > 16384 || c.height > 16384)
+            return fail(MERF_E_INVALID, "camera %d: size %dx%d out of range", i, c.width, c.height);
+        bool ok = std::isfinite(c.fx) && std::isfinite(c.fy) && std::isfinite(c.cx) && std::isfinite(c.cy) &&
+                  c.fx != 0.0f && c.fy != 0.0f;
+        for (int k = 0; k < 12; ++k) ok = ok && std::isfinite(c.c2w[k]);
+        if (!ok) return fail(MERF_E_INVALID, "camera %d: non-finite or zero intrinsics / pose", i);
+    }
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    int64_t pix = 0;
+    for (int first = 0; first < n_cams; first += kCamsPerLaunch) {
+        RenderBatch rb;
+        std::memset(&rb, 0, sizeof rb);
+        rb.n_cams = std::min(kCamsPerLaunch, n_cams - first);
+        rb.step = step;
+        rb.t_min = p->t_min;
+        rb.delta_mode = p->delta_mode;
+        rb.stats = reinterpret_cast<unsigned long long *>(p->stats_dev);
+        int64_t tiles = 0;
+        for (int i = 0; i < rb.n_cams; ++i) {
+            const merf_camera &c = cams[first + i];
+            DevCamera &dc = rb.cams[i];
+            std::memcpy(dc.c2w, c.c2w, sizeof dc.c2w);
+            dc.fx = c.fx; dc.fy = c.fy; dc.cx = c.cx; dc.cy = c.cy;
+            dc.width = c.width; dc.height = c.height;
+            dc.tiles_x = (c.width + kTile - 1) / kTile;
+            dc.tile_start = (int32_t)tiles;
+            dc.pix_start = pix;
+            tiles += (int64_t)dc.tiles_x * ((c.height + kTile - 1) / kTile);
+            pix += (int64_t)c.width * c.height;
+        }
+        if (tiles > INT32_MAX) return fail(MERF_E_INVALID, "too many pixels in one launch");
+        rb.total_tiles = (int32_t)tiles;
+        hipError_t e = launch_render(s->ds, rb, out_rgba_dev, stream);
+        if (e != hipSuccess) return hip_fail(e, "render launch");
+    }
+    return MERF_OK;
+}
+
+int merf_dequantize(const uint8_t *codes_dev, int64_t n, float m, int32_t prec, void *out_dev, void *hip_stream) {
+    g_error.clear();
+    if (n < 0) return fail(MERF_E_INVALID, "n %lld < 0", (long long)n);
+    if (n == 0) return MERF_OK;
+    if (!codes_dev || !out_dev) return fail(MERF_E_INVALID, "NULL buffer");
+    if (!(m > 0.0f) || !std::isfinite(m)) return fail(MERF_E_INVALID, "m %g must be positive", (double)m);
+    if (prec < 0 || prec > 2) return fail(MERF_E_INVALID, "prec %d not in {0, 1, 2}", prec);
+    hipError_t e = launch_dequant(codes_dev, n, m, prec, out_dev, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return hip_fail(e, "dequant launch");
+    return MERF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,61 @@
+// merf_device.h -- device-side scene layout and launch descriptors shared by
+// the host API (merf_api.hip) and the kernels (merf_render.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace merf {
+
+constexpr int kBlock = 8;                        // stored block edge (voxels)
+constexpr int kBrick = kBlock + 1;               // block plus a one-voxel apron on the high side
+constexpr int kChannels = 8;                     // density, rgb, 4 features
+constexpr int kBrickBytes = kBrick * kBrick * kBrick * kChannels;   // 5832
+constexpr int kMaxLevels = 4;
+constexpr int kMlpIn = 34;
+constexpr int kMlpHidden = 16;
+constexpr int kMlpOut = 3;
+constexpr int kMlpParams = kMlpIn * kMlpHidden + kMlpHidden + kMlpHidden * kMlpHidden + kMlpHidden +
+                           kMlpHidden * kMlpOut + kMlpOut;
+constexpr int kTile = 8;                         // a wave renders an 8x8 pixel tile
+constexpr int kCamsPerLaunch = 16;               // cameras carried in one launch's arguments
+
+// Scene as laid out in device memory.
+//   brick_index  int32 [(L/8)^3] z-major: brick slot or -1 (all codes 0).
+//   bricks       uint8 [n][9][9][9][8] (z, y, x, c): voxels 8b .. 8b+8 of each
+//                axis, so the 2x2x2 trilinear footprint whose low corner lies
+//                in block b is inside brick b.
+//   planes       uint8 [3][R][R][8]: P_x[z][y], P_y[z][x], P_z[y][x].
+//   occ[l]       uint8 [r^3] z-major, coarse to fine.
+//   mlp          float32 W0[34][16] b0 W1[16][16] b1 W2[16][3] b2.
+struct DevScene {
+    const int32_t *brick_index;
+    const uint8_t *bricks;
+    const uint8_t *planes;
+    const uint8_t *occ[kMaxLevels];
+    const float *mlp;
+    int32_t L, R, nbl, occ_levels;
+    int32_t occ_res[kMaxLevels];
+    float m_density, m_feature;
+};
+
+struct DevCamera {
+    float c2w[12];
+    float fx, fy, cx, cy;
+    int32_t width, height, tiles_x, tile_start;  // tile_start: first tile of this camera in the launch
+    int64_t pix_start;                           // first output pixel of this camera
+};
+
+struct RenderBatch {
+    int32_t n_cams, total_tiles;
+    float step, t_min;
+    int32_t delta_mode, pad;
+    unsigned long long *stats;
+    DevCamera cams[kCamsPerLaunch];
+};
+
+// Launchers (merf_render.hip).
+hipError_t launch_render(const DevScene &sc, const RenderBatch &rb, float *out, hipStream_t stream);
+hipError_t launch_dequant(const uint8_t *codes, int64_t n, float m, int prec, void *out, hipStream_t stream);
+
+}  // namespace merf

@@ -1,0 +1,506 @@
+// merf_render.hip -- gfx950 kernels of the MERF deferred volume renderer.
+//
+// One wave64 renders an 8x8 tile of pixels, one ray per lane, so the rays of
+// a wave are coherent and their plane and grid gathers fall on nearby texels.
+// Per lane (MERF, arXiv 2302.12249):
+//   1. pinhole ray (o, d);
+//   2. the ray is cut at the parameters where the region of the
+//      piecewise-projective contraction changes (Sec. 4.2, Eq. 7); each piece
+//      maps to a straight contracted segment, handled one at a time;
+//   3. each segment is marched on a uniform lattice of contracted step s
+//      (sample at each interval midpoint, last interval shortened); a sample
+//      is evaluated only if every occupancy level marks its cell occupied
+//      (Sec. 6); when a level reports an empty cell the march jumps to the
+//      first lattice sample past that cell's exit (ray-box slab test in
+//      contracted space, exact because the segment is straight);
+//   4. evaluated samples gather the 3D grid (trilinear, one brick per sample
+//      thanks to the apron) and the three planes (bilinear), dequantise each
+//      code (Eq. 8), sum (Eq. 5), decode (Eq. 6) -- density first, appearance
+//      only when alpha != 0 -- and composite (Eq. 1-2);
+//   5. marching stops when the transmittance drops below t_min (Sec. 6);
+//   6. the deferred MLP h(C_d, F, d) runs once per pixel (Eq. 3, App. B).
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "merf_device.h"
+
+namespace merf {
+
+namespace {
+
+constexpr float kInf = __builtin_huge_valf();
+constexpr float kRcp255 = 1.0f / 255.0f;
+// Samples are never skipped past a cell exit by more than this (contracted
+// units): FP32 error of the exit parameter is below 1e-6.
+constexpr float kSkipGuard = 2e-6f;
+
+// ---------------------------------------------------------------------------
+// Eq. 8: code b -> 2 m b / 255 - m, correctly rounded to float32.
+// k = m (2b - 255) is an exact small integer; q = k * RN(1/255) is then
+// corrected by one residual step (Markstein), which gives the correctly
+// rounded quotient k / 255 for every code and m in {7, 14} (checked
+// exhaustively by the test-suite).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float deq_f32(uint32_t b, float m2, float m255) {
+    float k = fmaf((float)b, m2, -m255);
+    float q = k * kRcp255;
+    float r = fmaf(-q, 255.0f, k);
+    return fmaf(r, kRcp255, q);
+}
+
+__device__ __forceinline__ uint32_t byte_of(uint32_t w, int i) { return (w >> (8 * i)) & 0xffu; }
+
+// ---------------------------------------------------------------------------
+// Eq. 7 regions: 0 = unit cube, 1 + 2j + (x_j < 0) = outer region of axis j.
+// Ties pick the first axis.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int region_of(float x, float y, float z) {
+    float ax = fabsf(x), ay = fabsf(y), az = fabsf(z);
+    int j = 0;
+    float r = ax, v = x;
+    if (ay > r) { r = ay; j = 1; v = y; }
+    if (az > r) { r = az; j = 2; v = z; }
+    if (r <= 1.0f) return 0;
+    return 1 + 2 * j + (v < 0.0f ? 1 : 0);
+}
+
+// Projective map of region reg (Eq. 7): y_j = (2 - 1/|x_j|) s, y_k = x_k/|x_j|.
+__device__ __forceinline__ float3 map_region(int reg, float3 x) {
+    if (reg == 0) return x;
+    int j = (reg - 1) >> 1;
+    float s = ((reg - 1) & 1) ? -1.0f : 1.0f;
+    float xj = j == 0 ? x.x : (j == 1 ? x.y : x.z);
+    float a = fabsf(xj);
+    float ia = 1.0f / a;
+    float3 y = make_float3(x.x * ia, x.y * ia, x.z * ia);
+    float yj = (2.0f - ia) * s;
+    if (j == 0) y.x = yj; else if (j == 1) y.y = yj; else y.z = yj;
+    return y;
+}
+
+// Contracted image of the ray's point at infinity in region reg.
+__device__ __forceinline__ float3 limit_point(int reg, float3 d) {
+    int j = (reg - 1) >> 1;
+    float s = ((reg - 1) & 1) ? -1.0f : 1.0f;
+    float dj = j == 0 ? d.x : (j == 1 ? d.y : d.z);
+    float ia = 1.0f / fabsf(dj);
+    float3 y = make_float3(d.x * ia, d.y * ia, d.z * ia);
+    if (j == 0) y.x = 2.0f * s; else if (j == 1) y.y = 2.0f * s; else y.z = 2.0f * s;
+    return y;
+}
+
+// Preimage of a contracted point in region reg (world-length deltas).
+__device__ __forceinline__ float3 unmap_region(int reg, float3 y) {
+    if (reg == 0) return y;
+    int j = (reg - 1) >> 1;
+    float s = ((reg - 1) & 1) ? -1.0f : 1.0f;
+    float yj = j == 0 ? y.x : (j == 1 ? y.y : y.z);
+    float a = 1.0f / (2.0f - s * yj);
+    float3 x = make_float3(y.x * a, y.y * a, y.z * a);
+    if (j == 0) x.x = s * a; else if (j == 1) x.y = s * a; else x.z = s * a;
+    return x;
+}
+
+struct Candidates {
+    float c[12];
+};
+
+__device__ __forceinline__ float valid_t(float t) { return (t > 0.0f && t < kInf) ? t : kInf; }
+
+// Parameters t > 0 where the ray can change region: x_j = +-1, x_j = +-x_k.
+__device__ __forceinline__ Candidates make_candidates(float3 o, float3 d) {
+    Candidates C;
+    C.c[0] = valid_t((1.0f - o.x) / d.x);
+    C.c[1] = valid_t((-1.0f - o.x) / d.x);
+    C.c[2] = valid_t((1.0f - o.y) / d.y);
+    C.c[3] = valid_t((-1.0f - o.y) / d.y);
+    C.c[4] = valid_t((1.0f - o.z) / d.z);
+    C.c[5] = valid_t((-1.0f - o.z) / d.z);
+    C.c[6] = valid_t((o.y - o.x) / (d.x - d.y));
+    C.c[7] = valid_t((-o.y - o.x) / (d.x + d.y));
+    C.c[8] = valid_t((o.z - o.x) / (d.x - d.z));
+    C.c[9] = valid_t((-o.z - o.x) / (d.x + d.z));
+    C.c[10] = valid_t((o.z - o.y) / (d.y - d.z));
+    C.c[11] = valid_t((-o.z - o.y) / (d.y + d.z));
+    return C;
+}
+
+// Smallest candidate strictly greater than t (kInf if none).
+__device__ __forceinline__ float next_candidate(const Candidates &C, float t) {
+    float m = kInf;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) m = (C.c[i] > t && C.c[i] < m) ? C.c[i] : m;
+    return m;
+}
+
+__device__ __forceinline__ int region_at(float3 o, float3 d, float t) {
+    return region_of(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+__device__ __forceinline__ float sigmoid(float x) { return 1.0f / (1.0f + __expf(-x)); }
+
+// XCD-aware tile order: consecutive workgroups are dispatched round-robin over
+// the 8 XCDs, so give each XCD a contiguous run of tiles (neighbouring tiles
+// gather neighbouring texels and share that XCD's L2).
+__device__ __forceinline__ int xcd_remap(int bid, int n) {
+    const int nx = 8;
+    int q = n / nx, r = n % nx;
+    int x = bid % nx, i = bid / nx;
+    return x * q + min(x, r) + i;
+}
+
+struct Accum {
+    float T, cd0, cd1, cd2, f0, f1, f2, f3;
+};
+
+struct Counters {
+    uint32_t occ_lookups, visited, evaluated, contributing;
+};
+
+// One evaluated sample: gather, dequantise, decode, composite.
+template <bool kStats>
+__device__ __forceinline__ void shade_sample(const DevScene &sc, float3 p, float delta, Accum &acc, Counters &cnt) {
+    // ---- sparse 3D grid: trilinear footprint inside one apron brick
+    const float gs = (float)sc.L * 0.25f, gmax = (float)(sc.L - 1);
+    float gx = fminf(fmaxf(fmaf(p.x + 2.0f, gs, -0.5f), 0.0f), gmax);
+    float gy = fminf(fmaxf(fmaf(p.y + 2.0f, gs, -0.5f), 0.0f), gmax);
+    float gz = fminf(fmaxf(fmaf(p.z + 2.0f, gs, -0.5f), 0.0f), gmax);
+    int ix = min((int)gx, sc.L - 2), iy = min((int)gy, sc.L - 2), iz = min((int)gz, sc.L - 2);
+    float fx = gx - (float)ix, fy = gy - (float)iy, fz = gz - (float)iz;
+    int brick = sc.brick_index[((iz >> 3) * sc.nbl + (iy >> 3)) * sc.nbl + (ix >> 3)];
+    uint2 g[8];
+    if (brick >= 0) {
+        const uint8_t *base = sc.bricks + (size_t)brick * kBrickBytes +
+                              (size_t)((((iz & 7) * kBrick + (iy & 7)) * kBrick + (ix & 7)) * kChannels);
+        constexpr int sy = kBrick * kChannels, sz = kBrick * kBrick * kChannels;
+        g[0] = *reinterpret_cast<const uint2 *>(base);
+        g[1] = *reinterpret_cast<const uint2 *>(base + 8);
+        g[2] = *reinterpret_cast<const uint2 *>(base + sy);
+        g[3] = *reinterpret_cast<const uint2 *>(base + sy + 8);
+        g[4] = *reinterpret_cast<const uint2 *>(base + sz);
+        g[5] = *reinterpret_cast<const uint2 *>(base + sz + 8);
+        g[6] = *reinterpret_cast<const uint2 *>(base + sz + sy);
+        g[7] = *reinterpret_cast<const uint2 *>(base + sz + sy + 8);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) g[i] = make_uint2(0u, 0u);
+    }
+    float wg[8];
+    {
+        float ax = 1.0f - fx, ay = 1.0f - fy, az = 1.0f - fz;
+        float w00 = ay * az, w10 = fy * az, w01 = ay * fz, w11 = fy * fz;
+        wg[0] = ax * w00; wg[1] = fx * w00; wg[2] = ax * w10; wg[3] = fx * w10;
+        wg[4] = ax * w01; wg[5] = fx * w01; wg[6] = ax * w11; wg[7] = fx * w11;
+    }
+    // ---- three planes: bilinear
+    const float ps = (float)sc.R * 0.25f, pmax = (float)(sc.R - 1);
+    float hx = fminf(fmaxf(fmaf(p.x + 2.0f, ps, -0.5f), 0.0f), pmax);
+    float hy = fminf(fmaxf(fmaf(p.y + 2.0f, ps, -0.5f), 0.0f), pmax);
+    float hz = fminf(fmaxf(fmaf(p.z + 2.0f, ps, -0.5f), 0.0f), pmax);
+    int jx = min((int)hx, sc.R - 2), jy = min((int)hy, sc.R - 2), jz = min((int)hz, sc.R - 2);
+    float ex = hx - (float)jx, ey = hy - (float)jy, ez = hz - (float)jz;
+    const size_t R = (size_t)sc.R, plane = R * R * kChannels, row = R * kChannels;
+    const uint8_t *p0 = sc.planes + (size_t)jz * row + (size_t)jy * kChannels;              // P_x(y, z)
+    const uint8_t *p1 = sc.planes + plane + (size_t)jz * row + (size_t)jx * kChannels;      // P_y(x, z)
+    const uint8_t *p2 = sc.planes + 2 * plane + (size_t)jy * row + (size_t)jx * kChannels;  // P_z(x, y)
+    uint2 t[12];
+    t[0] = *reinterpret_cast<const uint2 *>(p0);
+    t[1] = *reinterpret_cast<const uint2 *>(p0 + 8);
+    t[2] = *reinterpret_cast<const uint2 *>(p0 + row);
+    t[3] = *reinterpret_cast<const uint2 *>(p0 + row + 8);
+    t[4] = *reinterpret_cast<const uint2 *>(p1);
+    t[5] = *reinterpret_cast<const uint2 *>(p1 + 8);
+    t[6] = *reinterpret_cast<const uint2 *>(p1 + row);
+    t[7] = *reinterpret_cast<const uint2 *>(p1 + row + 8);
+    t[8] = *reinterpret_cast<const uint2 *>(p2);
+    t[9] = *reinterpret_cast<const uint2 *>(p2 + 8);
+    t[10] = *reinterpret_cast<const uint2 *>(p2 + row);
+    t[11] = *reinterpret_cast<const uint2 *>(p2 + row + 8);
+    float wp[12];
+    {
+        float a = 1.0f - ey, b = 1.0f - ez, c = 1.0f - ex;
+        wp[0] = a * b; wp[1] = ey * b; wp[2] = a * ez; wp[3] = ey * ez;      // (u=y, v=z)
+        wp[4] = c * b; wp[5] = ex * b; wp[6] = c * ez; wp[7] = ex * ez;      // (u=x, v=z)
+        wp[8] = c * a; wp[9] = ex * a; wp[10] = c * ey; wp[11] = ex * ey;    // (u=x, v=y)
+    }
+    // ---- density first (Sec. 6): appearance is read only when alpha != 0
+    const float md2 = 2.0f * sc.m_density, md255 = 255.0f * sc.m_density;
+    float s0 = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s0 = fmaf(wg[i], deq_f32(byte_of(g[i].x, 0), md2, md255), s0);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) s0 = fmaf(wp[i], deq_f32(byte_of(t[i].x, 0), md2, md255), s0);
+    float tau = __expf(s0);                       // Eq. 6
+    float trans = __expf(-tau * delta);           // e^{-tau delta} = 1 - alpha (Eq. 1)
+    float alpha = 1.0f - trans;
+    if (kStats) ++cnt.evaluated;
+    if (alpha > 0.0f) {
+        if (kStats) ++cnt.contributing;
+        const float mf2 = 2.0f * sc.m_feature, mf255 = 255.0f * sc.m_feature;
+        float s[7];
+#pragma unroll
+        for (int c = 0; c < 7; ++c) s[c] = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+#pragma unroll
+            for (int c = 1; c < 4; ++c) s[c - 1] = fmaf(wg[i], deq_f32(byte_of(g[i].x, c), mf2, mf255), s[c - 1]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) s[3 + c] = fmaf(wg[i], deq_f32(byte_of(g[i].y, c), mf2, mf255), s[3 + c]);
+        }
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+#pragma unroll
+            for (int c = 1; c < 4; ++c) s[c - 1] = fmaf(wp[i], deq_f32(byte_of(t[i].x, c), mf2, mf255), s[c - 1]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) s[3 + c] = fmaf(wp[i], deq_f32(byte_of(t[i].y, c), mf2, mf255), s[3 + c]);
+        }
+        float w = acc.T * alpha;                  // Eq. 1-2
+        acc.cd0 = fmaf(w, sigmoid(s[0]), acc.cd0);
+        acc.cd1 = fmaf(w, sigmoid(s[1]), acc.cd1);
+        acc.cd2 = fmaf(w, sigmoid(s[2]), acc.cd2);
+        acc.f0 = fmaf(w, sigmoid(s[3]), acc.f0);
+        acc.f1 = fmaf(w, sigmoid(s[4]), acc.f1);
+        acc.f2 = fmaf(w, sigmoid(s[5]), acc.f2);
+        acc.f3 = fmaf(w, sigmoid(s[6]), acc.f3);
+        acc.T *= trans;
+    }
+}
+
+// March one straight contracted segment A -> B of region reg.
+// Returns true when the ray terminated.
+template <bool kStats>
+__device__ __forceinline__ bool march_segment(const DevScene &sc, const RenderBatch &rb, int reg, float3 A, float3 B,
+                                              Accum &acc, Counters &cnt) {
+    float3 e = make_float3(B.x - A.x, B.y - A.y, B.z - A.z);
+    float len = sqrtf(e.x * e.x + e.y * e.y + e.z * e.z);
+    // contracted segments are at most a few units long; anything else is a
+    // degenerate ray (NaN / infinite end point) and contributes nothing
+    if (!(len > 0.0f && len < 16.0f)) return false;
+    float il = 1.0f / len;
+    e.x *= il; e.y *= il; e.z *= il;
+    const float step = rb.step, istep = 1.0f / step;
+    const int n = (int)ceilf(len / step);
+    // inverse direction for slab exits; axes with e = 0 never bound the exit
+    const float iex = e.x != 0.0f ? 1.0f / e.x : 0.0f;
+    const float iey = e.y != 0.0f ? 1.0f / e.y : 0.0f;
+    const float iez = e.z != 0.0f ? 1.0f / e.z : 0.0f;
+    int k = 0;
+    while (k < n) {
+        float u0 = (float)k * step;
+        float u1 = fminf(u0 + step, len);
+        float um = 0.5f * (u0 + u1);
+        float3 p = make_float3(fmaf(um, e.x, A.x), fmaf(um, e.y, A.y), fmaf(um, e.z, A.z));
+        if (kStats) ++cnt.visited;
+        // occupancy, coarse to fine
+        int empty = -1, cx = 0, cy = 0, cz = 0;
+#pragma unroll
+        for (int l = 0; l < kMaxLevels; ++l) {
+            if (l < sc.occ_levels && empty < 0) {
+                const int r = sc.occ_res[l];
+                const float os = (float)r * 0.25f;
+                int qx = clampi((int)floorf((p.x + 2.0f) * os), 0, r - 1);
+                int qy = clampi((int)floorf((p.y + 2.0f) * os), 0, r - 1);
+                int qz = clampi((int)floorf((p.z + 2.0f) * os), 0, r - 1);
+                if (kStats) ++cnt.occ_lookups;
+                if (!sc.occ[l][((size_t)qz * r + qy) * r + qx]) { empty = l; cx = qx; cy = qy; cz = qz; }
+            }
+        }
+        if (empty >= 0) {
+            // leave the empty cell: exit parameter along the segment (slab test)
+            int r = 0;
+#pragma unroll
+            for (int l = 0; l < kMaxLevels; ++l) r = (l == empty) ? sc.occ_res[l] : r;
+            const float h = 4.0f / (float)r;
+            float bx = (e.x > 0.0f ? (float)(cx + 1) : (float)cx) * h - 2.0f;
+            float by = (e.y > 0.0f ? (float)(cy + 1) : (float)cy) * h - 2.0f;
+            float bz = (e.z > 0.0f ? (float)(cz + 1) : (float)cz) * h - 2.0f;
+            float tx = e.x != 0.0f ? (bx - A.x) * iex : kInf;
+            float ty = e.y != 0.0f ? (by - A.y) * iey : kInf;
+            float tz = e.z != 0.0f ? (bz - A.z) * iez : kInf;
+            float uexit = fminf(tx, fminf(ty, tz));
+            // first lattice interval whose midpoint lies past the exit
+            float kn = floorf((uexit - kSkipGuard) * istep - 0.5f) + 1.0f;
+            int knext = kn > (float)n ? n : (int)fmaxf(kn, 0.0f);
+            k = max(k + 1, knext);
+            continue;
+        }
+        float delta = u1 - u0;
+        if (rb.delta_mode == 1) {
+            float3 y0 = make_float3(fmaf(u0, e.x, A.x), fmaf(u0, e.y, A.y), fmaf(u0, e.z, A.z));
+            float3 y1 = (k == n - 1) ? B : make_float3(fmaf(u1, e.x, A.x), fmaf(u1, e.y, A.y), fmaf(u1, e.z, A.z));
+            bool at_inf = false;
+            if (reg != 0) {
+                int j = (reg - 1) >> 1;
+                float s = ((reg - 1) & 1) ? -1.0f : 1.0f;
+                float y1j = j == 0 ? y1.x : (j == 1 ? y1.y : y1.z);
+                at_inf = s * y1j >= 2.0f;
+            }
+            if (at_inf) {
+                delta = kInf;
+            } else {
+                float3 x0 = unmap_region(reg, y0), x1 = unmap_region(reg, y1);
+                float dx = x1.x - x0.x, dy = x1.y - x0.y, dz = x1.z - x0.z;
+                delta = sqrtf(dx * dx + dy * dy + dz * dz);
+            }
+        }
+        shade_sample<kStats>(sc, p, delta, acc, cnt);
+        if (acc.T < rb.t_min) return true;        // early termination (Sec. 6)
+        ++k;
+    }
+    return false;
+}
+
+// Deferred MLP (Eq. 3, App. B): [C_d, F, d, sin(2^k d), cos(2^k d)] -> 16 -> 16 -> 3.
+// Weights are uniform across the wave and come in through the scalar cache.
+__device__ __forceinline__ float3 deferred_mlp(const float *__restrict__ W, const Accum &acc, float3 d) {
+    float x[kMlpIn];
+    x[0] = acc.cd0; x[1] = acc.cd1; x[2] = acc.cd2;
+    x[3] = acc.f0; x[4] = acc.f1; x[5] = acc.f2; x[6] = acc.f3;
+    x[7] = d.x; x[8] = d.y; x[9] = d.z;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        float sc = (float)(1 << k);
+        float sx, cx, sy, cy, sz, cz;
+        sincosf(d.x * sc, &sx, &cx);
+        sincosf(d.y * sc, &sy, &cy);
+        sincosf(d.z * sc, &sz, &cz);
+        x[10 + 3 * k] = sx; x[11 + 3 * k] = sy; x[12 + 3 * k] = sz;
+        x[22 + 3 * k] = cx; x[23 + 3 * k] = cy; x[24 + 3 * k] = cz;
+    }
+    const float *W0 = W, *b0 = W0 + kMlpIn * kMlpHidden, *W1 = b0 + kMlpHidden, *b1 = W1 + kMlpHidden * kMlpHidden,
+                *W2 = b1 + kMlpHidden, *b2 = W2 + kMlpHidden * kMlpOut;
+    float h1[kMlpHidden], h2[kMlpHidden];
+#pragma unroll
+    for (int o = 0; o < kMlpHidden; ++o) {
+        float a = b0[o];
+#pragma unroll
+        for (int i = 0; i < kMlpIn; ++i) a = fmaf(x[i], W0[i * kMlpHidden + o], a);
+        h1[o] = fmaxf(a, 0.0f);
+    }
+#pragma unroll
+    for (int o = 0; o < kMlpHidden; ++o) {
+        float a = b1[o];
+#pragma unroll
+        for (int i = 0; i < kMlpHidden; ++i) a = fmaf(h1[i], W1[i * kMlpHidden + o], a);
+        h2[o] = fmaxf(a, 0.0f);
+    }
+    float y[kMlpOut];
+#pragma unroll
+    for (int o = 0; o < kMlpOut; ++o) {
+        float a = b2[o];
+#pragma unroll
+        for (int i = 0; i < kMlpHidden; ++i) a = fmaf(h2[i], W2[i * kMlpOut + o], a);
+        y[o] = a;
+    }
+    return make_float3(y[0], y[1], y[2]);
+}
+
+template <bool kStats>
+__global__ __launch_bounds__(64) void k_render(const DevScene sc, const RenderBatch rb, float *__restrict__ out) {
+    const int tile = xcd_remap((int)blockIdx.x, rb.total_tiles);
+    int c = 0;
+#pragma unroll
+    for (int i = 1; i < kCamsPerLaunch; ++i)
+        if (i < rb.n_cams && tile >= rb.cams[i].tile_start) c = i;
+    const DevCamera &cam = rb.cams[c];
+    const int lt = tile - cam.tile_start;
+    const int lane = (int)threadIdx.x;
+    const int px = (lt % cam.tiles_x) * kTile + (lane & (kTile - 1));
+    const int py = (lt / cam.tiles_x) * kTile + (lane / kTile);
+    const bool active = px < cam.width && py < cam.height;
+
+    Counters cnt = {0u, 0u, 0u, 0u};
+    bool terminated = false;
+    if (active) {
+        // ---- pinhole ray
+        float vx = ((float)px + 0.5f - cam.cx) / cam.fx;
+        float vy = ((float)py + 0.5f - cam.cy) / cam.fy;
+        float3 d = make_float3(fmaf(cam.c2w[0], vx, fmaf(cam.c2w[1], vy, cam.c2w[2])),
+                               fmaf(cam.c2w[4], vx, fmaf(cam.c2w[5], vy, cam.c2w[6])),
+                               fmaf(cam.c2w[8], vx, fmaf(cam.c2w[9], vy, cam.c2w[10])));
+        float inv = 1.0f / sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
+        d.x *= inv; d.y *= inv; d.z *= inv;
+        const float3 o = make_float3(cam.c2w[3], cam.c2w[7], cam.c2w[11]);
+
+        // ---- contraction regions along the ray, one segment at a time
+        const Candidates C = make_candidates(o, d);
+        Accum acc = {1.0f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        float ta = 0.0f;
+        float c1 = next_candidate(C, 0.0f);
+        int reg = region_at(o, d, c1 < kInf ? 0.5f * c1 : 1.0f);
+        for (int seg = 0; seg < 8; ++seg) {
+            float tb = kInf, cur = ta;
+            int reg_next = reg;
+            for (int it = 0; it < 13; ++it) {
+                float n1 = next_candidate(C, cur);
+                if (!(n1 < kInf)) break;
+                float n2 = next_candidate(C, n1);
+                float tm = n2 < kInf ? 0.5f * (n1 + n2) : 2.0f * n1 + 1.0f;
+                int r2 = region_at(o, d, tm);
+                if (r2 != reg) { tb = n1; reg_next = r2; break; }
+                cur = n1;
+            }
+            float3 A = map_region(reg, make_float3(fmaf(ta, d.x, o.x), fmaf(ta, d.y, o.y), fmaf(ta, d.z, o.z)));
+            float3 B = tb < kInf ? map_region(reg, make_float3(fmaf(tb, d.x, o.x), fmaf(tb, d.y, o.y), fmaf(tb, d.z, o.z)))
+                                 : limit_point(reg, d);
+            if (march_segment<kStats>(sc, rb, reg, A, B, acc, cnt)) { terminated = true; break; }
+            if (!(tb < kInf)) break;
+            ta = tb;
+            reg = reg_next;
+        }
+        float3 h = deferred_mlp(sc.mlp, acc, d);
+        float4 rgba = make_float4(acc.cd0 + h.x, acc.cd1 + h.y, acc.cd2 + h.z, 1.0f - acc.T);
+        *reinterpret_cast<float4 *>(out + (cam.pix_start + (int64_t)py * cam.width + px) * 4) = rgba;
+    }
+    if (kStats) {
+        unsigned long long v[6] = {active ? 1ull : 0ull, cnt.occ_lookups, cnt.visited, cnt.evaluated, cnt.contributing,
+                                   terminated ? 1ull : 0ull};
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            unsigned long long x = v[i];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+            if (lane == 0 && x) atomicAdd(rb.stats + i, x);
+        }
+    }
+}
+
+// Eq. 8 dequantisation, correctly rounded to the output format.  Rounding the
+// correctly rounded float32 value again to float16 or bfloat16 gives the
+// correctly rounded result directly, because k/255 never lies within half a
+// float32 ulp of a float16 or bfloat16 rounding boundary (its binary
+// expansion repeats with period 8), and the test-suite checks all codes.
+__global__ void k_dequant(const uint8_t *__restrict__ codes, int64_t n, float m, int prec, void *__restrict__ out) {
+    const float m2 = 2.0f * m, m255 = 255.0f * m;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        float v = deq_f32(codes[i], m2, m255);
+        if (prec == 0) reinterpret_cast<float *>(out)[i] = v;
+        else if (prec == 1) reinterpret_cast<__half *>(out)[i] = __float2half_rn(v);
+        else reinterpret_cast<__hip_bfloat16 *>(out)[i] = __float2bfloat16(v);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_render(const DevScene &sc, const RenderBatch &rb, float *out, hipStream_t stream) {
+    if (rb.total_tiles <= 0) return hipSuccess;
+    dim3 grid((unsigned)rb.total_tiles), block(64);
+    if (rb.stats) hipLaunchKernelGGL(k_render<true>, grid, block, 0, stream, sc, rb, out);
+    else hipLaunchKernelGGL(k_render<false>, grid, block, 0, stream, sc, rb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_dequant(const uint8_t *codes, int64_t n, float m, int prec, void *out, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_dequant, dim3((unsigned)blocks), dim3(256), 0, stream, codes, n, m, prec, out);
+    return hipGetLastError();
+}
+
+}  // namespace merf

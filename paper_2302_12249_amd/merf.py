@@ -1,0 +1,224 @@
+"""ctypes binding of the C ABI in include/merf.h (argument marshalling only).
+
+Every step of rendering runs in the HIP library ``libmerf_hip.so`` built for
+gfx950; this module only converts numpy / torch arguments.  Importing it on a
+machine without the built library raises immediately: there is no fallback.
+PyTorch is used for device memory and streams only.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmerf_hip.so")
+
+MERF_OK = 0
+MERF_E_INVALID = -1
+MERF_E_OOM = -2
+MERF_E_DEVICE = -3
+MAX_OCC_LEVELS = 4
+STATS_FIELDS = ["rays", "occ_lookups", "visited", "evaluated", "contributing", "terminated"]
+
+PREC = {"f32": 0, "fp32": 0, "f16": 1, "fp16": 1, "bf16": 2}
+
+
+class MerfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"merf error {code}: {msg}")
+        self.code = code
+
+
+class merf_scene_desc(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("grid_res", C.c_int32), ("block_size", C.c_int32),
+                ("plane_res", C.c_int32), ("channels", C.c_int32), ("num_blocks", C.c_int32),
+                ("block_index", C.c_void_p), ("blocks", C.c_void_p), ("planes", C.c_void_p),
+                ("occ_levels", C.c_int32), ("occ_res", C.c_int32 * MAX_OCC_LEVELS),
+                ("occ", C.c_void_p * MAX_OCC_LEVELS), ("m_density", C.c_float), ("m_feature", C.c_float),
+                ("mlp_in", C.c_int32), ("mlp_hidden", C.c_int32), ("mlp_params", C.c_void_p)]
+
+
+class merf_camera(C.Structure):
+    _fields_ = [("c2w", C.c_float * 12), ("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float),
+                ("cy", C.c_float), ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class merf_render_params(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("step", C.c_float), ("t_min", C.c_float),
+                ("delta_mode", C.c_int32), ("mlp_prec", C.c_int32), ("feat_prec", C.c_int32),
+                ("stats_dev", C.c_void_p)]
+
+
+EXPORTS = ["merf_scene_upload", "merf_render", "merf_free", "merf_last_error", "merf_set_hbm_budget",
+           "merf_hbm_in_use", "merf_scene_bytes", "merf_dequantize"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = C.CDLL(path)
+    lib.merf_scene_upload.argtypes = [C.POINTER(merf_scene_desc), C.POINTER(C.c_void_p)]
+    lib.merf_scene_upload.restype = C.c_int
+    lib.merf_render.argtypes = [C.c_void_p, C.POINTER(merf_camera), C.c_int32, C.POINTER(merf_render_params),
+                                C.c_void_p, C.c_void_p]
+    lib.merf_render.restype = C.c_int
+    lib.merf_free.argtypes = [C.c_void_p]
+    lib.merf_free.restype = C.c_int
+    lib.merf_last_error.argtypes = []
+    lib.merf_last_error.restype = C.c_char_p
+    lib.merf_set_hbm_budget.argtypes = [C.c_size_t]
+    lib.merf_set_hbm_budget.restype = C.c_int
+    lib.merf_hbm_in_use.argtypes = []
+    lib.merf_hbm_in_use.restype = C.c_size_t
+    lib.merf_scene_bytes.argtypes = [C.c_void_p]
+    lib.merf_scene_bytes.restype = C.c_size_t
+    lib.merf_dequantize.argtypes = [C.c_void_p, C.c_int64, C.c_float, C.c_int32, C.c_void_p, C.c_void_p]
+    lib.merf_dequantize.restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().merf_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != MERF_OK:
+        raise MerfError(rc, last_error())
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def scene_desc(scene):
+    """Build a merf_scene_desc for a synth.Scene-like object.  Returns
+    (desc, keepalive) -- keepalive must outlive any call using desc."""
+    d = merf_scene_desc()
+    d.struct_size = C.sizeof(merf_scene_desc)
+    keep = []
+
+    def arr(a, dt):
+        a = np.ascontiguousarray(a, dt)
+        keep.append(a)
+        return a
+
+    bi = arr(scene.block_index, np.int32)
+    blocks = arr(scene.blocks, np.uint8)
+    planes = arr(scene.planes, np.uint8)
+    mlp = arr(scene.mlp, np.float32)
+    d.grid_res, d.block_size, d.plane_res, d.channels = scene.L, scene.B, scene.R, scene.C
+    d.num_blocks = int(blocks.shape[0])
+    d.block_index = _ptr(bi)
+    d.blocks = _ptr(blocks) if blocks.size else None
+    d.planes = _ptr(planes)
+    d.occ_levels = len(scene.occ)
+    for i, (r, o) in enumerate(scene.occ):
+        oo = arr(o, np.uint8)
+        d.occ_res[i] = int(r)
+        d.occ[i] = _ptr(oo)
+    d.m_density, d.m_feature = float(scene.m_density), float(scene.m_feature)
+    d.mlp_in, d.mlp_hidden = scene.mlp_in, scene.mlp_hidden
+    d.mlp_params = _ptr(mlp)
+    return d, keep
+
+
+def scene_upload(scene) -> int:
+    """merf_scene_upload: returns the opaque scene handle (an int)."""
+    lib = load()
+    d, keep = scene_desc(scene)
+    h = C.c_void_p()
+    _check(lib.merf_scene_upload(C.byref(d), C.byref(h)))
+    del keep
+    return h.value
+
+
+def merf_free(handle: int):
+    _check(load().merf_free(C.c_void_p(handle)))
+
+
+def set_hbm_budget(nbytes: int):
+    _check(load().merf_set_hbm_budget(int(nbytes)))
+
+
+def hbm_in_use() -> int:
+    return int(load().merf_hbm_in_use())
+
+
+def scene_bytes(handle: int) -> int:
+    return int(load().merf_scene_bytes(C.c_void_p(handle)))
+
+
+def camera_array(cams):
+    """merf_camera[n] from a synth.Cameras-like object."""
+    n = len(cams)
+    arr = (merf_camera * max(n, 1))()
+    for i in range(n):
+        c = arr[i]
+        for k, v in enumerate(np.asarray(cams.c2w[i], np.float32).reshape(12)):
+            c.c2w[k] = float(v)
+        c.fx, c.fy, c.cx, c.cy = [float(v) for v in np.asarray(cams.intr[i], np.float32)]
+        c.width, c.height = int(cams.size[i, 0]), int(cams.size[i, 1])
+    return arr
+
+
+def render_params(step: float = 0.0, t_min: float = 2e-4, delta_mode: int = 0, mlp_prec="f32",
+                  feat_prec="f32", stats_ptr: Optional[int] = None) -> merf_render_params:
+    p = merf_render_params()
+    p.struct_size = C.sizeof(merf_render_params)
+    p.step, p.t_min, p.delta_mode = float(step), float(t_min), int(delta_mode)
+    p.mlp_prec = PREC[mlp_prec] if isinstance(mlp_prec, str) else int(mlp_prec)
+    p.feat_prec = PREC[feat_prec] if isinstance(feat_prec, str) else int(feat_prec)
+    p.stats_dev = stats_ptr
+    return p
+
+
+def merf_render(handle: int, cam_arr, n_cams: int, params: merf_render_params, out_ptr: int, stream_ptr: int = 0):
+    """Raw merf_render: cam_arr from camera_array(), out_ptr a device pointer."""
+    _check(load().merf_render(C.c_void_p(handle), cam_arr, int(n_cams), C.byref(params), C.c_void_p(out_ptr),
+                              C.c_void_p(stream_ptr)))
+
+
+def merf_dequantize(codes_ptr: int, n: int, m: float, prec: int, out_ptr: int, stream_ptr: int = 0):
+    _check(load().merf_dequantize(C.c_void_p(codes_ptr), int(n), float(m), int(prec), C.c_void_p(out_ptr),
+                                  C.c_void_p(stream_ptr)))
+
+
+class Renderer:
+    """Convenience wrapper: one resident scene rendered into torch tensors."""
+
+    def __init__(self, scene):
+        self.scene = scene
+        self.handle = scene_upload(scene)
+
+    def close(self):
+        if self.handle:
+            merf_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def render(self, cams, out=None, stream=None, stats=None, **kw):
+        """Render cams into a [pixels, 4] float32 cuda tensor (allocated if out is None)."""
+        import torch
+        n = cams.num_pixels()
+        if out is None:
+            out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+        assert out.is_cuda and out.dtype == torch.float32 and out.is_contiguous() and out.numel() >= 4 * n
+        st = stream if stream is not None else torch.cuda.current_stream()
+        p = render_params(stats_ptr=stats.data_ptr() if stats is not None else None, **kw)
+        merf_render(self.handle, camera_array(cams), len(cams), p, out.data_ptr(), st.cuda_stream)
+        return out
