@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="after timing, run a plain device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this renderer runs on one GPU; --gpus {args.gpus} is not supported "
@@ -155,6 +157,16 @@ def main():
                     "visited": visited / n_rays, "occ_lookups": occ_lookups / n_rays},
         "alg_bytes_per_launch": alg_bytes,
     }
+    if args.copy_probe_mb > 0:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters read
+        # exactly copy_probe_mb MiB each when the counters are exact
+        src = torch.ones(args.copy_probe_mb << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        res["copy_probe_bytes"] = src.numel() * 4
+        del src, dst
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(scene, cams, args.cpu_seconds)
     print(json.dumps(res), flush=True)
