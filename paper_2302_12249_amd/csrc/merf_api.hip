@@ -103,7 +103,8 @@ int validate_desc(const merf_scene_desc *d) {
 }
 
 // Bricks with a one-voxel apron: brick (bx, by, bz) holds voxels 8b .. 8b+8 of
-// each axis.  A brick is needed when any of the 8 blocks it touches is stored.
+// each axis.  A brick is stored when any of the 8 blocks it touches is stored;
+// all other index entries point at one shared all-zero brick (the last).
 void build_bricks(const merf_scene_desc *d, std::vector<int32_t> &bidx, std::vector<uint8_t> &bricks) {
     const int L = d->grid_res, nbl = L / kBlock;
     auto block_at = [&](int bx, int by, int bz) -> int32_t {
@@ -121,12 +122,17 @@ void build_bricks(const merf_scene_desc *d, std::vector<int32_t> &bidx, std::vec
                         for (int dx = 0; dx < 2 && !need; ++dx) need = block_at(bx + dx, by + dy, bz + dz) >= 0;
                 if (need) bidx[((size_t)bz * nbl + by) * nbl + bx] = n++;
             }
-    bricks.assign((size_t)n * kBrickBytes, 0);
+    // one extra all-zero brick stands for every absent brick, so the kernel
+    // never branches on the index
+    const int32_t zero = n;
+    for (int32_t &b : bidx)
+        if (b < 0) b = zero;
+    bricks.assign((size_t)(n + 1) * kBrickBytes, 0);
     for (int bz = 0; bz < nbl; ++bz)
         for (int by = 0; by < nbl; ++by)
             for (int bx = 0; bx < nbl; ++bx) {
                 int32_t slot = bidx[((size_t)bz * nbl + by) * nbl + bx];
-                if (slot < 0) continue;
+                if (slot == zero) continue;
                 uint8_t *dst = bricks.data() + (size_t)slot * kBrickBytes;
                 for (int lz = 0; lz < kBrick; ++lz)
                     for (int ly = 0; ly < kBrick; ++ly)

@@ -21,7 +21,8 @@ constexpr int kTile = 8;                         // a wave renders an 8x8 pixel 
 constexpr int kCamsPerLaunch = 16;               // cameras carried in one launch's arguments
 
 // Scene as laid out in device memory.
-//   brick_index  int32 [(L/8)^3] z-major: brick slot or -1 (all codes 0).
+//   brick_index  int32 [(L/8)^3] z-major: brick slot; blocks whose brick would
+//                hold only zeros point at a shared all-zero brick.
 //   bricks       uint8 [n][9][9][9][8] (z, y, x, c): voxels 8b .. 8b+8 of each
 //                axis, so the 2x2x2 trilinear footprint whose low corner lies
 //                in block b is inside brick b.

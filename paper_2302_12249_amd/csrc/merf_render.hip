@@ -162,79 +162,94 @@ struct Counters {
     uint32_t occ_lookups, visited, evaluated, contributing;
 };
 
+template <typename T>
+__device__ __forceinline__ T load_at(const uint8_t *base, uint32_t off) {
+    return *reinterpret_cast<const T *>(base + off);
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// 16-byte load (two adjacent 8-byte texels) that stays one instruction: the
+// empty asm consumes the whole vector, so the compiler cannot split it into
+// per-word loads and sink the appearance words behind the alpha test.
+__device__ __forceinline__ u32x4 load_pair(const uint8_t *base, uint32_t off) {
+    u32x4 v = *reinterpret_cast<const u32x4 *>(base + off);
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 // One evaluated sample: gather, dequantise, decode, composite.
+// All offsets are 32-bit (the upload keeps every array below 2 GiB) and are
+// added to uniform base pointers, so no 64-bit address arithmetic runs per lane.
 template <bool kStats>
 __device__ __forceinline__ void shade_sample(const DevScene &sc, float3 p, float delta, Accum &acc, Counters &cnt) {
-    // ---- sparse 3D grid: trilinear footprint inside one apron brick
-    const float gs = (float)sc.L * 0.25f, gmax = (float)(sc.L - 1);
-    float gx = fminf(fmaxf(fmaf(p.x + 2.0f, gs, -0.5f), 0.0f), gmax);
-    float gy = fminf(fmaxf(fmaf(p.y + 2.0f, gs, -0.5f), 0.0f), gmax);
-    float gz = fminf(fmaxf(fmaf(p.z + 2.0f, gs, -0.5f), 0.0f), gmax);
-    int ix = min((int)gx, sc.L - 2), iy = min((int)gy, sc.L - 2), iz = min((int)gz, sc.L - 2);
-    float fx = gx - (float)ix, fy = gy - (float)iy, fz = gz - (float)iz;
-    int brick = sc.brick_index[((iz >> 3) * sc.nbl + (iy >> 3)) * sc.nbl + (ix >> 3)];
-    uint2 g[8];
-    if (brick >= 0) {
-        const uint8_t *base = sc.bricks + (size_t)brick * kBrickBytes +
-                              (size_t)((((iz & 7) * kBrick + (iy & 7)) * kBrick + (ix & 7)) * kChannels);
-        constexpr int sy = kBrick * kChannels, sz = kBrick * kBrick * kChannels;
-        g[0] = *reinterpret_cast<const uint2 *>(base);
-        g[1] = *reinterpret_cast<const uint2 *>(base + 8);
-        g[2] = *reinterpret_cast<const uint2 *>(base + sy);
-        g[3] = *reinterpret_cast<const uint2 *>(base + sy + 8);
-        g[4] = *reinterpret_cast<const uint2 *>(base + sz);
-        g[5] = *reinterpret_cast<const uint2 *>(base + sz + 8);
-        g[6] = *reinterpret_cast<const uint2 *>(base + sz + sy);
-        g[7] = *reinterpret_cast<const uint2 *>(base + sz + sy + 8);
-    } else {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) g[i] = make_uint2(0u, 0u);
-    }
-    float wg[8];
-    {
-        float ax = 1.0f - fx, ay = 1.0f - fy, az = 1.0f - fz;
-        float w00 = ay * az, w10 = fy * az, w01 = ay * fz, w11 = fy * fz;
-        wg[0] = ax * w00; wg[1] = fx * w00; wg[2] = ax * w10; wg[3] = fx * w10;
-        wg[4] = ax * w01; wg[5] = fx * w01; wg[6] = ax * w11; wg[7] = fx * w11;
-    }
-    // ---- three planes: bilinear
+    // ---- three planes: bilinear.  Their addresses depend on no load, so they
+    // are issued first and overlap the brick-index round trip below.
     const float ps = (float)sc.R * 0.25f, pmax = (float)(sc.R - 1);
     float hx = fminf(fmaxf(fmaf(p.x + 2.0f, ps, -0.5f), 0.0f), pmax);
     float hy = fminf(fmaxf(fmaf(p.y + 2.0f, ps, -0.5f), 0.0f), pmax);
     float hz = fminf(fmaxf(fmaf(p.z + 2.0f, ps, -0.5f), 0.0f), pmax);
     int jx = min((int)hx, sc.R - 2), jy = min((int)hy, sc.R - 2), jz = min((int)hz, sc.R - 2);
     float ex = hx - (float)jx, ey = hy - (float)jy, ez = hz - (float)jz;
-    const size_t R = (size_t)sc.R, plane = R * R * kChannels, row = R * kChannels;
-    const uint8_t *p0 = sc.planes + (size_t)jz * row + (size_t)jy * kChannels;              // P_x(y, z)
-    const uint8_t *p1 = sc.planes + plane + (size_t)jz * row + (size_t)jx * kChannels;      // P_y(x, z)
-    const uint8_t *p2 = sc.planes + 2 * plane + (size_t)jy * row + (size_t)jx * kChannels;  // P_z(x, y)
-    uint2 t[12];
-    t[0] = *reinterpret_cast<const uint2 *>(p0);
-    t[1] = *reinterpret_cast<const uint2 *>(p0 + 8);
-    t[2] = *reinterpret_cast<const uint2 *>(p0 + row);
-    t[3] = *reinterpret_cast<const uint2 *>(p0 + row + 8);
-    t[4] = *reinterpret_cast<const uint2 *>(p1);
-    t[5] = *reinterpret_cast<const uint2 *>(p1 + 8);
-    t[6] = *reinterpret_cast<const uint2 *>(p1 + row);
-    t[7] = *reinterpret_cast<const uint2 *>(p1 + row + 8);
-    t[8] = *reinterpret_cast<const uint2 *>(p2);
-    t[9] = *reinterpret_cast<const uint2 *>(p2 + 8);
-    t[10] = *reinterpret_cast<const uint2 *>(p2 + row);
-    t[11] = *reinterpret_cast<const uint2 *>(p2 + row + 8);
-    float wp[12];
+    const uint32_t row = (uint32_t)sc.R * kChannels, plane = (uint32_t)sc.R * row;
+    const uint32_t o0 = (uint32_t)jz * row + (uint32_t)jy * kChannels;              // P_x(y, z)
+    const uint32_t o1 = plane + (uint32_t)jz * row + (uint32_t)jx * kChannels;      // P_y(x, z)
+    const uint32_t o2 = 2u * plane + (uint32_t)jy * row + (uint32_t)jx * kChannels; // P_z(x, y)
+    u32x4 t[6];   // each = texels (u, v) and (u + 1, v)
+    t[0] = load_pair(sc.planes, o0);
+    t[1] = load_pair(sc.planes, o0 + row);
+    t[2] = load_pair(sc.planes, o1);
+    t[3] = load_pair(sc.planes, o1 + row);
+    t[4] = load_pair(sc.planes, o2);
+    t[5] = load_pair(sc.planes, o2 + row);
+    // ---- sparse 3D grid: trilinear footprint inside one apron brick.  Every
+    // index entry is a valid brick (absent blocks point at an all-zero brick),
+    // so the corner loads need no branch.
+    const float gs = (float)sc.L * 0.25f, gmax = (float)(sc.L - 1);
+    float gx = fminf(fmaxf(fmaf(p.x + 2.0f, gs, -0.5f), 0.0f), gmax);
+    float gy = fminf(fmaxf(fmaf(p.y + 2.0f, gs, -0.5f), 0.0f), gmax);
+    float gz = fminf(fmaxf(fmaf(p.z + 2.0f, gs, -0.5f), 0.0f), gmax);
+    int ix = min((int)gx, sc.L - 2), iy = min((int)gy, sc.L - 2), iz = min((int)gz, sc.L - 2);
+    float fx = gx - (float)ix, fy = gy - (float)iy, fz = gz - (float)iz;
+    const uint32_t bi = ((uint32_t)(iz >> 3) * sc.nbl + (uint32_t)(iy >> 3)) * sc.nbl + (uint32_t)(ix >> 3);
+    const int brick = load_at<int>(reinterpret_cast<const uint8_t *>(sc.brick_index), bi * 4u);
+    const uint32_t ob = (uint32_t)brick * kBrickBytes +
+                        (uint32_t)((((iz & 7) * kBrick + (iy & 7)) * kBrick + (ix & 7)) * kChannels);
+    constexpr uint32_t sy = kBrick * kChannels, sz = kBrick * kBrick * kChannels;
+    u32x4 g[4];   // corners (x, x + 1) at (y, z), (y + 1, z), (y, z + 1), (y + 1, z + 1)
+    g[0] = load_pair(sc.bricks, ob);
+    g[1] = load_pair(sc.bricks, ob + sy);
+    g[2] = load_pair(sc.bricks, ob + sz);
+    g[3] = load_pair(sc.bricks, ob + sz + sy);
+    // texel words: lo = channels 0..3, hi = channels 4..7
+    uint32_t lo[20], hi[20];
+    float w[20];
     {
-        float a = 1.0f - ey, b = 1.0f - ez, c = 1.0f - ex;
-        wp[0] = a * b; wp[1] = ey * b; wp[2] = a * ez; wp[3] = ey * ez;      // (u=y, v=z)
-        wp[4] = c * b; wp[5] = ex * b; wp[6] = c * ez; wp[7] = ex * ez;      // (u=x, v=z)
-        wp[8] = c * a; wp[9] = ex * a; wp[10] = c * ey; wp[11] = ex * ey;    // (u=x, v=y)
+        float ax = 1.0f - fx, ay = 1.0f - fy, az = 1.0f - fz;
+        float w00 = ay * az, w10 = fy * az, w01 = ay * fz, w11 = fy * fz;
+        const float wyz[4] = {w00, w10, w01, w11};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            lo[2 * i] = g[i].x; hi[2 * i] = g[i].y; w[2 * i] = ax * wyz[i];
+            lo[2 * i + 1] = g[i].z; hi[2 * i + 1] = g[i].w; w[2 * i + 1] = fx * wyz[i];
+        }
+        // planes: (u, v) weights; u/v axes are (y, z), (x, z), (x, y)
+        const float fu[3] = {ey, ex, ex}, fv[3] = {ez, ez, ey};
+#pragma unroll
+        for (int pl = 0; pl < 3; ++pl) {
+            const float au = 1.0f - fu[pl], av = 1.0f - fv[pl];
+            const u32x4 r0 = t[2 * pl], r1 = t[2 * pl + 1];
+            lo[8 + 4 * pl] = r0.x; hi[8 + 4 * pl] = r0.y; w[8 + 4 * pl] = au * av;
+            lo[9 + 4 * pl] = r0.z; hi[9 + 4 * pl] = r0.w; w[9 + 4 * pl] = fu[pl] * av;
+            lo[10 + 4 * pl] = r1.x; hi[10 + 4 * pl] = r1.y; w[10 + 4 * pl] = au * fv[pl];
+            lo[11 + 4 * pl] = r1.z; hi[11 + 4 * pl] = r1.w; w[11 + 4 * pl] = fu[pl] * fv[pl];
+        }
     }
     // ---- density first (Sec. 6): appearance is read only when alpha != 0
     const float md2 = 2.0f * sc.m_density, md255 = 255.0f * sc.m_density;
     float s0 = 0.0f;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) s0 = fmaf(wg[i], deq_f32(byte_of(g[i].x, 0), md2, md255), s0);
-#pragma unroll
-    for (int i = 0; i < 12; ++i) s0 = fmaf(wp[i], deq_f32(byte_of(t[i].x, 0), md2, md255), s0);
+    for (int i = 0; i < 20; ++i) s0 = fmaf(w[i], deq_f32(byte_of(lo[i], 0), md2, md255), s0);
     float tau = __expf(s0);                       // Eq. 6
     float trans = __expf(-tau * delta);           // e^{-tau delta} = 1 - alpha (Eq. 1)
     float alpha = 1.0f - trans;
@@ -246,162 +261,159 @@ __device__ __forceinline__ void shade_sample(const DevScene &sc, float3 p, float
 #pragma unroll
         for (int c = 0; c < 7; ++c) s[c] = 0.0f;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 0; i < 20; ++i) {
 #pragma unroll
-            for (int c = 1; c < 4; ++c) s[c - 1] = fmaf(wg[i], deq_f32(byte_of(g[i].x, c), mf2, mf255), s[c - 1]);
+            for (int c = 1; c < 4; ++c) s[c - 1] = fmaf(w[i], deq_f32(byte_of(lo[i], c), mf2, mf255), s[c - 1]);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) s[3 + c] = fmaf(wg[i], deq_f32(byte_of(g[i].y, c), mf2, mf255), s[3 + c]);
+            for (int c = 0; c < 4; ++c) s[3 + c] = fmaf(w[i], deq_f32(byte_of(hi[i], c), mf2, mf255), s[3 + c]);
         }
-#pragma unroll
-        for (int i = 0; i < 12; ++i) {
-#pragma unroll
-            for (int c = 1; c < 4; ++c) s[c - 1] = fmaf(wp[i], deq_f32(byte_of(t[i].x, c), mf2, mf255), s[c - 1]);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) s[3 + c] = fmaf(wp[i], deq_f32(byte_of(t[i].y, c), mf2, mf255), s[3 + c]);
-        }
-        float w = acc.T * alpha;                  // Eq. 1-2
-        acc.cd0 = fmaf(w, sigmoid(s[0]), acc.cd0);
-        acc.cd1 = fmaf(w, sigmoid(s[1]), acc.cd1);
-        acc.cd2 = fmaf(w, sigmoid(s[2]), acc.cd2);
-        acc.f0 = fmaf(w, sigmoid(s[3]), acc.f0);
-        acc.f1 = fmaf(w, sigmoid(s[4]), acc.f1);
-        acc.f2 = fmaf(w, sigmoid(s[5]), acc.f2);
-        acc.f3 = fmaf(w, sigmoid(s[6]), acc.f3);
+        float wt = acc.T * alpha;                 // Eq. 1-2
+        acc.cd0 = fmaf(wt, sigmoid(s[0]), acc.cd0);
+        acc.cd1 = fmaf(wt, sigmoid(s[1]), acc.cd1);
+        acc.cd2 = fmaf(wt, sigmoid(s[2]), acc.cd2);
+        acc.f0 = fmaf(wt, sigmoid(s[3]), acc.f0);
+        acc.f1 = fmaf(wt, sigmoid(s[4]), acc.f1);
+        acc.f2 = fmaf(wt, sigmoid(s[5]), acc.f2);
+        acc.f3 = fmaf(wt, sigmoid(s[6]), acc.f3);
         acc.T *= trans;
     }
 }
 
-// March one straight contracted segment A -> B of region reg.
-// Returns true when the ray terminated.
-template <bool kStats>
-__device__ __forceinline__ bool march_segment(const DevScene &sc, const RenderBatch &rb, int reg, float3 A, float3 B,
-                                              Accum &acc, Counters &cnt) {
-    float3 e = make_float3(B.x - A.x, B.y - A.y, B.z - A.z);
+// March state of one straight contracted segment A -> B (region reg) that
+// covers the world parameters [ta, tb] of the ray.
+struct Segment {
+    float3 A, B, e;                 // contracted start, end, unit direction
+    float len, iex, iey, iez;       // length; inverse direction (0 where e = 0)
+    float tb;                       // world parameter of the end (kInf: last)
+    int n, k, reg, reg_next;        // interval count, next interval, regions
+};
+
+// Set up the segment of the ray that starts at world parameter ta in region
+// reg: find where the region next changes (Eq. 7 breakpoints), map both ends.
+__device__ __forceinline__ void open_segment(float3 o, float3 d, float ta, int reg, float step, Segment &s) {
+    const Candidates C = make_candidates(o, d);
+    float tb = kInf, cur = ta;
+    int reg_next = reg;
+    for (int it = 0; it < 13; ++it) {
+        float n1 = next_candidate(C, cur);
+        if (!(n1 < kInf)) break;
+        float n2 = next_candidate(C, n1);
+        float tm = n2 < kInf ? 0.5f * (n1 + n2) : 2.0f * n1 + 1.0f;
+        int r2 = region_at(o, d, tm);
+        if (r2 != reg) { tb = n1; reg_next = r2; break; }
+        cur = n1;
+    }
+    s.A = map_region(reg, make_float3(fmaf(ta, d.x, o.x), fmaf(ta, d.y, o.y), fmaf(ta, d.z, o.z)));
+    s.B = tb < kInf ? map_region(reg, make_float3(fmaf(tb, d.x, o.x), fmaf(tb, d.y, o.y), fmaf(tb, d.z, o.z)))
+                    : limit_point(reg, d);
+    s.tb = tb;
+    s.reg = reg;
+    s.reg_next = reg_next;
+    float3 e = make_float3(s.B.x - s.A.x, s.B.y - s.A.y, s.B.z - s.A.z);
     float len = sqrtf(e.x * e.x + e.y * e.y + e.z * e.z);
+    s.k = 0;
     // contracted segments are at most a few units long; anything else is a
     // degenerate ray (NaN / infinite end point) and contributes nothing
-    if (!(len > 0.0f && len < 16.0f)) return false;
+    if (!(len > 0.0f && len < 16.0f)) {
+        s.n = 0;
+        s.len = 0.0f;
+        return;
+    }
     float il = 1.0f / len;
     e.x *= il; e.y *= il; e.z *= il;
-    const float step = rb.step, istep = 1.0f / step;
-    const int n = (int)ceilf(len / step);
-    // inverse direction for slab exits; axes with e = 0 never bound the exit
-    const float iex = e.x != 0.0f ? 1.0f / e.x : 0.0f;
-    const float iey = e.y != 0.0f ? 1.0f / e.y : 0.0f;
-    const float iez = e.z != 0.0f ? 1.0f / e.z : 0.0f;
-    int k = 0;
-    while (k < n) {
-        float u0 = (float)k * step;
-        float u1 = fminf(u0 + step, len);
-        float um = 0.5f * (u0 + u1);
-        float3 p = make_float3(fmaf(um, e.x, A.x), fmaf(um, e.y, A.y), fmaf(um, e.z, A.z));
-        if (kStats) ++cnt.visited;
-        // occupancy, coarse to fine
-        int empty = -1, cx = 0, cy = 0, cz = 0;
-#pragma unroll
-        for (int l = 0; l < kMaxLevels; ++l) {
-            if (l < sc.occ_levels && empty < 0) {
-                const int r = sc.occ_res[l];
-                const float os = (float)r * 0.25f;
-                int qx = clampi((int)floorf((p.x + 2.0f) * os), 0, r - 1);
-                int qy = clampi((int)floorf((p.y + 2.0f) * os), 0, r - 1);
-                int qz = clampi((int)floorf((p.z + 2.0f) * os), 0, r - 1);
-                if (kStats) ++cnt.occ_lookups;
-                if (!sc.occ[l][((size_t)qz * r + qy) * r + qx]) { empty = l; cx = qx; cy = qy; cz = qz; }
-            }
-        }
-        if (empty >= 0) {
-            // leave the empty cell: exit parameter along the segment (slab test)
-            int r = 0;
-#pragma unroll
-            for (int l = 0; l < kMaxLevels; ++l) r = (l == empty) ? sc.occ_res[l] : r;
-            const float h = 4.0f / (float)r;
-            float bx = (e.x > 0.0f ? (float)(cx + 1) : (float)cx) * h - 2.0f;
-            float by = (e.y > 0.0f ? (float)(cy + 1) : (float)cy) * h - 2.0f;
-            float bz = (e.z > 0.0f ? (float)(cz + 1) : (float)cz) * h - 2.0f;
-            float tx = e.x != 0.0f ? (bx - A.x) * iex : kInf;
-            float ty = e.y != 0.0f ? (by - A.y) * iey : kInf;
-            float tz = e.z != 0.0f ? (bz - A.z) * iez : kInf;
-            float uexit = fminf(tx, fminf(ty, tz));
-            // first lattice interval whose midpoint lies past the exit
-            float kn = floorf((uexit - kSkipGuard) * istep - 0.5f) + 1.0f;
-            int knext = kn > (float)n ? n : (int)fmaxf(kn, 0.0f);
-            k = max(k + 1, knext);
-            continue;
-        }
-        float delta = u1 - u0;
-        if (rb.delta_mode == 1) {
-            float3 y0 = make_float3(fmaf(u0, e.x, A.x), fmaf(u0, e.y, A.y), fmaf(u0, e.z, A.z));
-            float3 y1 = (k == n - 1) ? B : make_float3(fmaf(u1, e.x, A.x), fmaf(u1, e.y, A.y), fmaf(u1, e.z, A.z));
-            bool at_inf = false;
-            if (reg != 0) {
-                int j = (reg - 1) >> 1;
-                float s = ((reg - 1) & 1) ? -1.0f : 1.0f;
-                float y1j = j == 0 ? y1.x : (j == 1 ? y1.y : y1.z);
-                at_inf = s * y1j >= 2.0f;
-            }
-            if (at_inf) {
-                delta = kInf;
-            } else {
-                float3 x0 = unmap_region(reg, y0), x1 = unmap_region(reg, y1);
-                float dx = x1.x - x0.x, dy = x1.y - x0.y, dz = x1.z - x0.z;
-                delta = sqrtf(dx * dx + dy * dy + dz * dz);
-            }
-        }
-        shade_sample<kStats>(sc, p, delta, acc, cnt);
-        if (acc.T < rb.t_min) return true;        // early termination (Sec. 6)
-        ++k;
-    }
-    return false;
+    s.e = e;
+    s.len = len;
+    s.n = (int)ceilf(len / step);
+    s.iex = e.x != 0.0f ? 1.0f / e.x : 0.0f;
+    s.iey = e.y != 0.0f ? 1.0f / e.y : 0.0f;
+    s.iez = e.z != 0.0f ? 1.0f / e.z : 0.0f;
 }
 
-// Deferred MLP (Eq. 3, App. B): [C_d, F, d, sin(2^k d), cos(2^k d)] -> 16 -> 16 -> 3.
-// Weights are uniform across the wave and come in through the scalar cache.
-__device__ __forceinline__ float3 deferred_mlp(const float *__restrict__ W, const Accum &acc, float3 d) {
-    float x[kMlpIn];
+// Deferred MLP (Eq. 3, App. B) for the 64 pixels of a wave on the matrix
+// cores.  Each layer is computed transposed, H^T = W^T X^T, with
+// v_mfma_f32_16x16x4f32 over 4 blocks of 16 pixels: the output of one layer
+// (lane l holds hidden units 4(l/16) .. +3 of pixel l % 16) is exactly the
+// B operand the next layer needs, so only the input features and the final
+// RGB pass through LDS.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+constexpr int kXStride = 37;      // LDS row stride (floats) of the 36-wide padded input
+
+__device__ __forceinline__ void mlp_encode(float *x, const Accum &acc, float3 d) {
     x[0] = acc.cd0; x[1] = acc.cd1; x[2] = acc.cd2;
     x[3] = acc.f0; x[4] = acc.f1; x[5] = acc.f2; x[6] = acc.f3;
     x[7] = d.x; x[8] = d.y; x[9] = d.z;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        float sc = (float)(1 << k);
-        float sx, cx, sy, cy, sz, cz;
-        sincosf(d.x * sc, &sx, &cx);
-        sincosf(d.y * sc, &sy, &cy);
-        sincosf(d.z * sc, &sz, &cz);
-        x[10 + 3 * k] = sx; x[11 + 3 * k] = sy; x[12 + 3 * k] = sz;
-        x[22 + 3 * k] = cx; x[23 + 3 * k] = cy; x[24 + 3 * k] = cz;
+        const float sc = (float)(1 << k);
+        x[10 + 3 * k] = __sinf(d.x * sc); x[11 + 3 * k] = __sinf(d.y * sc); x[12 + 3 * k] = __sinf(d.z * sc);
+        x[22 + 3 * k] = __cosf(d.x * sc); x[23 + 3 * k] = __cosf(d.y * sc); x[24 + 3 * k] = __cosf(d.z * sc);
     }
+    x[34] = 0.0f;
+    x[35] = 0.0f;
+}
+
+// Returns h(x) for this lane's pixel.  All 64 lanes must call it.
+__device__ __forceinline__ float3 deferred_mlp_mfma(const float *__restrict__ W, float *xs, const Accum &acc,
+                                                    float3 d) {
+    const int lane = (int)threadIdx.x, j = lane & 15, g = lane >> 4;
     const float *W0 = W, *b0 = W0 + kMlpIn * kMlpHidden, *W1 = b0 + kMlpHidden, *b1 = W1 + kMlpHidden * kMlpHidden,
                 *W2 = b1 + kMlpHidden, *b2 = W2 + kMlpHidden * kMlpOut;
-    float h1[kMlpHidden], h2[kMlpHidden];
+    {
+        float x[36];
+        mlp_encode(x, acc, d);
 #pragma unroll
-    for (int o = 0; o < kMlpHidden; ++o) {
-        float a = b0[o];
+        for (int i = 0; i < 36; ++i) xs[lane * kXStride + i] = x[i];
+    }
+    // layer-1 A operand: W0^T[hidden j][k] for k = 9g + ks (zero past 34)
+    float a0[9];
 #pragma unroll
-        for (int i = 0; i < kMlpIn; ++i) a = fmaf(x[i], W0[i * kMlpHidden + o], a);
-        h1[o] = fmaxf(a, 0.0f);
+    for (int ks = 0; ks < 9; ++ks) {
+        const int k = 9 * g + ks;
+        a0[ks] = k < kMlpIn ? W0[k * kMlpHidden + j] : 0.0f;
+    }
+    __syncthreads();
+    floatx4 h1[4], h2[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        floatx4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+        const float *xr = xs + (16 * mt + j) * kXStride + 9 * g;
+#pragma unroll
+        for (int ks = 0; ks < 9; ++ks) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks], xr[ks], c, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) h1[mt][r] = fmaxf(c[r] + b0[4 * g + r], 0.0f);
+    }
+    float a1[4], a2[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+        a1[ks] = W1[(4 * g + ks) * kMlpHidden + j];
+        a2[ks] = j < kMlpOut ? W2[(4 * g + ks) * kMlpOut + j] : 0.0f;
     }
 #pragma unroll
-    for (int o = 0; o < kMlpHidden; ++o) {
-        float a = b1[o];
+    for (int mt = 0; mt < 4; ++mt) {
+        floatx4 c = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int i = 0; i < kMlpHidden; ++i) a = fmaf(h1[i], W1[i * kMlpHidden + o], a);
-        h2[o] = fmaxf(a, 0.0f);
+        for (int ks = 0; ks < 4; ++ks) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks], h1[mt][ks], c, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) h2[mt][r] = fmaxf(c[r] + b1[4 * g + r], 0.0f);
     }
-    float y[kMlpOut];
+    __syncthreads();   // every lane has read its layer-1 inputs; reuse xs for the outputs
 #pragma unroll
-    for (int o = 0; o < kMlpOut; ++o) {
-        float a = b2[o];
+    for (int mt = 0; mt < 4; ++mt) {
+        floatx4 c = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int i = 0; i < kMlpHidden; ++i) a = fmaf(h2[i], W2[i * kMlpOut + o], a);
-        y[o] = a;
+        for (int ks = 0; ks < 4; ++ks) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[ks], h2[mt][ks], c, 0, 0, 0);
+        if (g == 0) {
+#pragma unroll
+            for (int r = 0; r < kMlpOut; ++r) xs[(16 * mt + j) * kXStride + r] = c[r] + b2[r];
+        }
     }
-    return make_float3(y[0], y[1], y[2]);
+    __syncthreads();
+    return make_float3(xs[lane * kXStride + 0], xs[lane * kXStride + 1], xs[lane * kXStride + 2]);
 }
 
 template <bool kStats>
 __global__ __launch_bounds__(64) void k_render(const DevScene sc, const RenderBatch rb, float *__restrict__ out) {
+    __shared__ float xs[64 * kXStride];
     const int tile = xcd_remap((int)blockIdx.x, rb.total_tiles);
     int c = 0;
 #pragma unroll
@@ -414,46 +426,116 @@ __global__ __launch_bounds__(64) void k_render(const DevScene sc, const RenderBa
     const int py = (lt / cam.tiles_x) * kTile + (lane / kTile);
     const bool active = px < cam.width && py < cam.height;
 
-    Counters cnt = {0u, 0u, 0u, 0u};
-    bool terminated = false;
-    if (active) {
-        // ---- pinhole ray
-        float vx = ((float)px + 0.5f - cam.cx) / cam.fx;
-        float vy = ((float)py + 0.5f - cam.cy) / cam.fy;
-        float3 d = make_float3(fmaf(cam.c2w[0], vx, fmaf(cam.c2w[1], vy, cam.c2w[2])),
-                               fmaf(cam.c2w[4], vx, fmaf(cam.c2w[5], vy, cam.c2w[6])),
-                               fmaf(cam.c2w[8], vx, fmaf(cam.c2w[9], vy, cam.c2w[10])));
-        float inv = 1.0f / sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
-        d.x *= inv; d.y *= inv; d.z *= inv;
-        const float3 o = make_float3(cam.c2w[3], cam.c2w[7], cam.c2w[11]);
+    // ---- pinhole ray
+    float vx = ((float)px + 0.5f - cam.cx) / cam.fx;
+    float vy = ((float)py + 0.5f - cam.cy) / cam.fy;
+    float3 d = make_float3(fmaf(cam.c2w[0], vx, fmaf(cam.c2w[1], vy, cam.c2w[2])),
+                           fmaf(cam.c2w[4], vx, fmaf(cam.c2w[5], vy, cam.c2w[6])),
+                           fmaf(cam.c2w[8], vx, fmaf(cam.c2w[9], vy, cam.c2w[10])));
+    float inv = 1.0f / sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
+    d.x *= inv; d.y *= inv; d.z *= inv;
+    const float3 o = make_float3(cam.c2w[3], cam.c2w[7], cam.c2w[11]);
 
-        // ---- contraction regions along the ray, one segment at a time
+    Counters cnt = {0u, 0u, 0u, 0u};
+    Accum acc = {1.0f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const float step = rb.step, istep = 1.0f / step;
+    Segment s;
+    {
         const Candidates C = make_candidates(o, d);
-        Accum acc = {1.0f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        float ta = 0.0f;
-        float c1 = next_candidate(C, 0.0f);
-        int reg = region_at(o, d, c1 < kInf ? 0.5f * c1 : 1.0f);
-        for (int seg = 0; seg < 8; ++seg) {
-            float tb = kInf, cur = ta;
-            int reg_next = reg;
-            for (int it = 0; it < 13; ++it) {
-                float n1 = next_candidate(C, cur);
-                if (!(n1 < kInf)) break;
-                float n2 = next_candidate(C, n1);
-                float tm = n2 < kInf ? 0.5f * (n1 + n2) : 2.0f * n1 + 1.0f;
-                int r2 = region_at(o, d, tm);
-                if (r2 != reg) { tb = n1; reg_next = r2; break; }
-                cur = n1;
+        const float c1 = next_candidate(C, 0.0f);
+        open_segment(o, d, 0.0f, region_at(o, d, c1 < kInf ? 0.5f * c1 : 1.0f), step, s);
+    }
+    int nseg = 1;
+    bool alive = active, terminated = false;
+
+    // Each round: every live lane advances to its next occupied sample (cheap
+    // skip iterations), then all lanes that found one shade it together, so
+    // the expensive gather-and-composite code runs with as many lanes as
+    // possible.
+    while (__any(alive)) {
+        bool found = false;
+        float3 p = make_float3(0.f, 0.f, 0.f);
+        float delta = 0.0f;
+        while (alive && !found) {
+            if (s.k >= s.n) {
+                // segment done: continue in the next region, if any
+                if (!(s.tb < kInf) || nseg >= 8) { alive = false; break; }
+                open_segment(o, d, s.tb, s.reg_next, step, s);
+                ++nseg;
+                continue;
             }
-            float3 A = map_region(reg, make_float3(fmaf(ta, d.x, o.x), fmaf(ta, d.y, o.y), fmaf(ta, d.z, o.z)));
-            float3 B = tb < kInf ? map_region(reg, make_float3(fmaf(tb, d.x, o.x), fmaf(tb, d.y, o.y), fmaf(tb, d.z, o.z)))
-                                 : limit_point(reg, d);
-            if (march_segment<kStats>(sc, rb, reg, A, B, acc, cnt)) { terminated = true; break; }
-            if (!(tb < kInf)) break;
-            ta = tb;
-            reg = reg_next;
+            const float u0 = (float)s.k * step;
+            const float u1 = fminf(u0 + step, s.len);
+            const float um = 0.5f * (u0 + u1);
+            p = make_float3(fmaf(um, s.e.x, s.A.x), fmaf(um, s.e.y, s.A.y), fmaf(um, s.e.z, s.A.z));
+            if (kStats) ++cnt.visited;
+            // occupancy, coarse to fine: stop at the first empty level
+            int empty = -1, cx = 0, cy = 0, cz = 0, r = 1;
+#pragma unroll
+            for (int l = 0; l < kMaxLevels; ++l) {
+                if (l < sc.occ_levels && empty < 0) {
+                    const int rl = sc.occ_res[l];
+                    const float os = (float)rl * 0.25f;
+                    int qx = clampi((int)floorf((p.x + 2.0f) * os), 0, rl - 1);
+                    int qy = clampi((int)floorf((p.y + 2.0f) * os), 0, rl - 1);
+                    int qz = clampi((int)floorf((p.z + 2.0f) * os), 0, rl - 1);
+                    if (kStats) ++cnt.occ_lookups;
+                    if (!sc.occ[l][((uint32_t)qz * rl + qy) * rl + qx]) {
+                        empty = l; cx = qx; cy = qy; cz = qz; r = rl;
+                    }
+                }
+            }
+            if (empty < 0) {
+                found = true;
+                delta = u1 - u0;
+                if (rb.delta_mode == 1) {
+                    float3 y0 = make_float3(fmaf(u0, s.e.x, s.A.x), fmaf(u0, s.e.y, s.A.y), fmaf(u0, s.e.z, s.A.z));
+                    float3 y1 = (s.k == s.n - 1)
+                                    ? s.B
+                                    : make_float3(fmaf(u1, s.e.x, s.A.x), fmaf(u1, s.e.y, s.A.y), fmaf(u1, s.e.z, s.A.z));
+                    bool at_inf = false;
+                    if (s.reg != 0) {
+                        const int jj = (s.reg - 1) >> 1;
+                        const float sg = ((s.reg - 1) & 1) ? -1.0f : 1.0f;
+                        const float y1j = jj == 0 ? y1.x : (jj == 1 ? y1.y : y1.z);
+                        at_inf = sg * y1j >= 2.0f;
+                    }
+                    if (at_inf) {
+                        delta = kInf;
+                    } else {
+                        float3 x0 = unmap_region(s.reg, y0), x1 = unmap_region(s.reg, y1);
+                        float dx = x1.x - x0.x, dy = x1.y - x0.y, dz = x1.z - x0.z;
+                        delta = sqrtf(dx * dx + dy * dy + dz * dz);
+                    }
+                }
+                break;
+            }
+            // leave the empty cell: exit parameter along the segment (slab test)
+            const float h = 4.0f / (float)r;
+            float bx = (s.e.x > 0.0f ? (float)(cx + 1) : (float)cx) * h - 2.0f;
+            float by = (s.e.y > 0.0f ? (float)(cy + 1) : (float)cy) * h - 2.0f;
+            float bz = (s.e.z > 0.0f ? (float)(cz + 1) : (float)cz) * h - 2.0f;
+            float tx = s.e.x != 0.0f ? (bx - s.A.x) * s.iex : kInf;
+            float ty = s.e.y != 0.0f ? (by - s.A.y) * s.iey : kInf;
+            float tz = s.e.z != 0.0f ? (bz - s.A.z) * s.iez : kInf;
+            float uexit = fminf(tx, fminf(ty, tz));
+            // first lattice interval whose midpoint lies past the exit
+            float kn = floorf((uexit - kSkipGuard) * istep - 0.5f) + 1.0f;
+            int knext = kn > (float)s.n ? s.n : (int)fmaxf(kn, 0.0f);
+            s.k = max(s.k + 1, knext);
         }
-        float3 h = deferred_mlp(sc.mlp, acc, d);
+        if (found) {
+            shade_sample<kStats>(sc, p, delta, acc, cnt);
+            ++s.k;
+            if (acc.T < rb.t_min) {          // early termination (Sec. 6)
+                alive = false;
+                terminated = true;
+            }
+        }
+    }
+
+    const float3 h = deferred_mlp_mfma(sc.mlp, xs, acc, d);
+    if (active) {
         float4 rgba = make_float4(acc.cd0 + h.x, acc.cd1 + h.y, acc.cd2 + h.z, 1.0f - acc.T);
         *reinterpret_cast<float4 *>(out + (cam.pix_start + (int64_t)py * cam.width + px) * 4) = rgba;
     }
