@@ -69,8 +69,12 @@ def cpu_baseline(scene, cams, seconds: float):
     out, _ = oracle.render(os_, cams, rows_stride=stride, row_offset=stride // 2, fragile=False, stats=False)
     dt = time.perf_counter() - t0
     n = out.shape[0]
-    return {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": f"every {stride}th row of the {W}x{H} frame ({n} rays, {dt:.1f} s, FP64 C, OpenMP)"}
+    import numpy as np
+    rows = np.arange(stride // 2, H, stride)
+    sel = (rows[:, None] * W + np.arange(W)[None, :]).reshape(-1)
+    return ({"value": n / dt / 1e6, "unit": "Mrays/s", "cores": oracle.max_threads(), "kind": "oracle",
+             "sample": f"every {stride}th row of the {W}x{H} frame ({n} rays, {dt:.1f} s, FP64 C, OpenMP)"},
+            (out, sel))
 
 
 def main():
@@ -125,7 +129,6 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     per = np.array([a.elapsed_time(b) for a, b in ev])          # ms, GPU time per frame
-    r.close()
 
     ms_per_step = wall * 1e3 / args.steps
     kernel_ms = float(per.mean())
@@ -157,6 +160,23 @@ def main():
                     "visited": visited / n_rays, "occ_lookups": occ_lookups / n_rays},
         "alg_bytes_per_launch": alg_bytes,
     }
+    # precision variants of the deferred MLP (fp16 / bf16 inputs on MFMA,
+    # fp32 accumulation); compositing and transmittance stay fp32
+    prec = {}
+    for name in ("f16", "bf16"):
+        img = torch.empty_like(out)
+        for _ in range(3):
+            r.render(cams, out=img, mlp_prec=name)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(20):
+            r.render(cams, out=img, mlp_prec=name)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 20
+        prec[name] = {"mlp": name, "kernel_ms": ms, "Mrays/s": rays / (ms * 1e-3) / 1e6, "_img": img}
+    res["precision"] = prec
     if args.copy_probe_mb > 0:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters read
         # exactly copy_probe_mb MiB each when the counters are exact
@@ -167,8 +187,22 @@ def main():
         torch.cuda.synchronize()
         res["copy_probe_bytes"] = src.numel() * 4
         del src, dst
+    images = {"f32": out.cpu().numpy()}
+    for name, v in prec.items():
+        images[name] = v.pop("_img").cpu().numpy()
+    r.close()
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(scene, cams, args.cpu_seconds)
+        res["cpu_baseline"], (ref, sel) = cpu_baseline(scene, cams, args.cpu_seconds)
+        # accuracy of each path against the FP64 oracle on the same rows
+        for name, img in images.items():
+            d = img[sel].astype(np.float64) - ref
+            mse = float(np.mean(d[:, :3] ** 2))
+            acc = {"psnr_db": 10.0 * np.log10(1.0 / max(mse, 1e-30)), "max_abs": float(np.abs(d).max()),
+                   "mean_abs": float(np.abs(d).mean()), "pixels": int(len(sel))}
+            if name == "f32":
+                res["accuracy_f32"] = acc
+            else:
+                res["precision"][name].update(acc)
     print(json.dumps(res), flush=True)
 
 

@@ -296,7 +296,7 @@ int merf_render(merf_scene_t s, const merf_camera *cams, int32_t n_cams, const m
     if (!std::isfinite(step) || step < 1e-6f) return fail(MERF_E_INVALID, "step %g out of range", (double)p->step);
     if (!(p->t_min >= 0.0f && p->t_min < 1.0f)) return fail(MERF_E_INVALID, "t_min %g not in [0, 1)", (double)p->t_min);
     if (p->delta_mode != 0 && p->delta_mode != 1) return fail(MERF_E_INVALID, "delta_mode %d", p->delta_mode);
-    if (p->mlp_prec != 0) return fail(MERF_E_INVALID, "mlp_prec %d not supported", p->mlp_prec);
+    if (p->mlp_prec < 0 || p->mlp_prec > 2) return fail(MERF_E_INVALID, "mlp_prec %d not in {0, 1, 2}", p->mlp_prec);
     if (p->feat_prec != 0) return fail(MERF_E_INVALID, "feat_prec %d not supported", p->feat_prec);
     for (int i = 0; i < n_cams; ++i) {
         const merf_camera &c = cams[i];
@@ -316,6 +316,7 @@ int merf_render(merf_scene_t s, const merf_camera *cams, int32_t n_cams, const m
         rb.step = step;
         rb.t_min = p->t_min;
         rb.delta_mode = p->delta_mode;
+        rb.mlp_prec = p->mlp_prec;
         rb.stats = reinterpret_cast<unsigned long long *>(p->stats_dev);
         int64_t tiles = 0;
         for (int i = 0; i < rb.n_cams; ++i) {

@@ -50,7 +50,7 @@ struct DevCamera {
 struct RenderBatch {
     int32_t n_cams, total_tiles;
     float step, t_min;
-    int32_t delta_mode, pad;
+    int32_t delta_mode, mlp_prec;
     unsigned long long *stats;
     DevCamera cams[kCamsPerLaunch];
 };

@@ -245,28 +245,36 @@ __device__ __forceinline__ void shade_sample(const DevScene &sc, float3 p, float
             lo[11 + 4 * pl] = r1.z; hi[11 + 4 * pl] = r1.w; w[11 + 4 * pl] = fu[pl] * fv[pl];
         }
     }
+    // ---- Eq. 8 dequantises each code affinely, q(b) = a b - m with a = 2m/255,
+    // and the 20 weights form four partitions of unity (one per source), so
+    // sum_i w_i q(b_i) = a * sum_i w_i b_i - 4m exactly.  Interpolating the
+    // codes and applying the affine map once per channel computes the same
+    // real number with one convert and one FMA per texel and channel; the two
+    // FP32 evaluations differ by rounding only (below 1e-6 relative).
     // ---- density first (Sec. 6): appearance is read only when alpha != 0
-    const float md2 = 2.0f * sc.m_density, md255 = 255.0f * sc.m_density;
     float s0 = 0.0f;
 #pragma unroll
-    for (int i = 0; i < 20; ++i) s0 = fmaf(w[i], deq_f32(byte_of(lo[i], 0), md2, md255), s0);
-    float tau = __expf(s0);                       // Eq. 6
+    for (int i = 0; i < 20; ++i) s0 = fmaf(w[i], (float)byte_of(lo[i], 0), s0);
+    const float md = sc.m_density, mf = sc.m_feature;
+    float tau = __expf(fmaf(s0, md * (2.0f / 255.0f), -4.0f * md));   // Eq. 6
     float trans = __expf(-tau * delta);           // e^{-tau delta} = 1 - alpha (Eq. 1)
     float alpha = 1.0f - trans;
     if (kStats) ++cnt.evaluated;
     if (alpha > 0.0f) {
         if (kStats) ++cnt.contributing;
-        const float mf2 = 2.0f * sc.m_feature, mf255 = 255.0f * sc.m_feature;
         float s[7];
 #pragma unroll
         for (int c = 0; c < 7; ++c) s[c] = 0.0f;
 #pragma unroll
         for (int i = 0; i < 20; ++i) {
 #pragma unroll
-            for (int c = 1; c < 4; ++c) s[c - 1] = fmaf(w[i], deq_f32(byte_of(lo[i], c), mf2, mf255), s[c - 1]);
+            for (int c = 1; c < 4; ++c) s[c - 1] = fmaf(w[i], (float)byte_of(lo[i], c), s[c - 1]);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) s[3 + c] = fmaf(w[i], deq_f32(byte_of(hi[i], c), mf2, mf255), s[3 + c]);
+            for (int c = 0; c < 4; ++c) s[3 + c] = fmaf(w[i], (float)byte_of(hi[i], c), s[3 + c]);
         }
+        const float af = mf * (2.0f / 255.0f), bf = -4.0f * mf;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) s[c] = fmaf(s[c], af, bf);
         float wt = acc.T * alpha;                 // Eq. 1-2
         acc.cd0 = fmaf(wt, sigmoid(s[0]), acc.cd0);
         acc.cd1 = fmaf(wt, sigmoid(s[1]), acc.cd1);
@@ -330,12 +338,18 @@ __device__ __forceinline__ void open_segment(float3 o, float3 d, float ta, int r
 }
 
 // Deferred MLP (Eq. 3, App. B) for the 64 pixels of a wave on the matrix
-// cores.  Each layer is computed transposed, H^T = W^T X^T, with
-// v_mfma_f32_16x16x4f32 over 4 blocks of 16 pixels: the output of one layer
-// (lane l holds hidden units 4(l/16) .. +3 of pixel l % 16) is exactly the
-// B operand the next layer needs, so only the input features and the final
-// RGB pass through LDS.
+// cores.  Each layer is computed transposed, H^T = W^T X^T, over 4 blocks of
+// 16 pixels: the output of one layer (lane l holds hidden units 4(l/16) .. +3
+// of pixel l % 16) is exactly the B operand the next layer needs, so only the
+// input features and the final RGB pass through LDS.  A pixel is a column of
+// every product, so inactive lanes cannot affect the others.
+//   kPrec 0: fp32 inputs, v_mfma_f32_16x16x4f32 (K = 4 per instruction);
+//   kPrec 1: fp16 inputs, v_mfma_f32_16x16x16f16 (K = 16);
+//   kPrec 2: bf16 inputs, v_mfma_f32_16x16x16bf16_1k (K = 16).
+// Accumulation, biases and ReLU are fp32 in every case.
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef _Float16 halfx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 constexpr int kXStride = 37;      // LDS row stride (floats) of the 36-wide padded input
 
 __device__ __forceinline__ void mlp_encode(float *x, const Accum &acc, float3 d) {
@@ -352,7 +366,23 @@ __device__ __forceinline__ void mlp_encode(float *x, const Accum &acc, float3 d)
     x[35] = 0.0f;
 }
 
+// 16x16 block product with K = 16 in half precision: lane l supplies
+// A[l % 16][4(l/16) .. +3] and B[4(l/16) .. +3][l % 16].
+template <int kPrec>
+__device__ __forceinline__ floatx4 mfma16(const float a[4], const float b[4], floatx4 c) {
+    if constexpr (kPrec == 1) {
+        halfx4 ha = {(_Float16)a[0], (_Float16)a[1], (_Float16)a[2], (_Float16)a[3]};
+        halfx4 hb = {(_Float16)b[0], (_Float16)b[1], (_Float16)b[2], (_Float16)b[3]};
+        return __builtin_amdgcn_mfma_f32_16x16x16f16(ha, hb, c, 0, 0, 0);
+    } else {
+        bf16x4 ha = {(__bf16)a[0], (__bf16)a[1], (__bf16)a[2], (__bf16)a[3]};
+        bf16x4 hb = {(__bf16)b[0], (__bf16)b[1], (__bf16)b[2], (__bf16)b[3]};
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ha, hb, c, 0, 0, 0);
+    }
+}
+
 // Returns h(x) for this lane's pixel.  All 64 lanes must call it.
+template <int kPrec>
 __device__ __forceinline__ float3 deferred_mlp_mfma(const float *__restrict__ W, float *xs, const Accum &acc,
                                                     float3 d) {
     const int lane = (int)threadIdx.x, j = lane & 15, g = lane >> 4;
@@ -364,54 +394,67 @@ __device__ __forceinline__ float3 deferred_mlp_mfma(const float *__restrict__ W,
 #pragma unroll
         for (int i = 0; i < 36; ++i) xs[lane * kXStride + i] = x[i];
     }
-    // layer-1 A operand: W0^T[hidden j][k] for k = 9g + ks (zero past 34)
-    float a0[9];
+    // layer-1 A operand W0^T[hidden j][k]: fp32 steps take k = 9g + q,
+    // half-precision steps k = 16 (q / 4) + 4g + q % 4 (zero past 34)
+    constexpr int kA0 = kPrec == 0 ? 9 : 12;
+    float a0[kA0], a1[4], a2[4];
 #pragma unroll
-    for (int ks = 0; ks < 9; ++ks) {
-        const int k = 9 * g + ks;
-        a0[ks] = k < kMlpIn ? W0[k * kMlpHidden + j] : 0.0f;
+    for (int q = 0; q < kA0; ++q) {
+        const int k = kPrec == 0 ? 9 * g + q : 16 * (q >> 2) + 4 * g + (q & 3);
+        a0[q] = k < kMlpIn ? W0[k * kMlpHidden + j] : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        a1[q] = W1[(4 * g + q) * kMlpHidden + j];
+        a2[q] = j < kMlpOut ? W2[(4 * g + q) * kMlpOut + j] : 0.0f;
     }
     __syncthreads();
-    floatx4 h1[4], h2[4];
+    floatx4 y[4];
+    // one block of 16 pixels at a time through all three layers
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
+        const float *xr = xs + (16 * mt + j) * kXStride;
         floatx4 c = {0.0f, 0.0f, 0.0f, 0.0f};
-        const float *xr = xs + (16 * mt + j) * kXStride + 9 * g;
+        if constexpr (kPrec == 0) {
 #pragma unroll
-        for (int ks = 0; ks < 9; ++ks) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks], xr[ks], c, 0, 0, 0);
+            for (int q = 0; q < 9; ++q) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[q], xr[9 * g + q], c, 0, 0, 0);
+        } else {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) h1[mt][r] = fmaxf(c[r] + b0[4 * g + r], 0.0f);
-    }
-    float a1[4], a2[4];
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-        a1[ks] = W1[(4 * g + ks) * kMlpHidden + j];
-        a2[ks] = j < kMlpOut ? W2[(4 * g + ks) * kMlpOut + j] : 0.0f;
-    }
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-        floatx4 c = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks], h1[mt][ks], c, 0, 0, 0);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) h2[mt][r] = fmaxf(c[r] + b1[4 * g + r], 0.0f);
-    }
-    __syncthreads();   // every lane has read its layer-1 inputs; reuse xs for the outputs
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-        floatx4 c = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[ks], h2[mt][ks], c, 0, 0, 0);
-        if (g == 0) {
-#pragma unroll
-            for (int r = 0; r < kMlpOut; ++r) xs[(16 * mt + j) * kXStride + r] = c[r] + b2[r];
+            for (int ks = 0; ks < 3; ++ks) c = mfma16<kPrec>(a0 + 4 * ks, xr + 16 * ks + 4 * g, c);
         }
+        float h[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) h[r] = fmaxf(c[r] + b0[4 * g + r], 0.0f);
+        c = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        if constexpr (kPrec == 0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[q], h[q], c, 0, 0, 0);
+        } else {
+            c = mfma16<kPrec>(a1, h, c);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) h[r] = fmaxf(c[r] + b1[4 * g + r], 0.0f);
+        c = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        if constexpr (kPrec == 0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[q], h[q], c, 0, 0, 0);
+        } else {
+            c = mfma16<kPrec>(a2, h, c);
+        }
+        y[mt] = c;
+    }
+    __syncthreads();   // every lane has read its inputs; reuse xs for the outputs
+    if (g == 0) {
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int r = 0; r < kMlpOut; ++r) xs[(16 * mt + j) * kXStride + r] = y[mt][r] + b2[r];
     }
     __syncthreads();
     return make_float3(xs[lane * kXStride + 0], xs[lane * kXStride + 1], xs[lane * kXStride + 2]);
 }
 
-template <bool kStats>
+template <bool kStats, int kMlpPrec>
 __global__ __launch_bounds__(64) void k_render(const DevScene sc, const RenderBatch rb, float *__restrict__ out) {
     __shared__ float xs[64 * kXStride];
     const int tile = xcd_remap((int)blockIdx.x, rb.total_tiles);
@@ -534,7 +577,7 @@ __global__ __launch_bounds__(64) void k_render(const DevScene sc, const RenderBa
         }
     }
 
-    const float3 h = deferred_mlp_mfma(sc.mlp, xs, acc, d);
+    const float3 h = deferred_mlp_mfma<kMlpPrec>(sc.mlp, xs, acc, d);
     if (active) {
         float4 rgba = make_float4(acc.cd0 + h.x, acc.cd1 + h.y, acc.cd2 + h.z, 1.0f - acc.T);
         *reinterpret_cast<float4 *>(out + (cam.pix_start + (int64_t)py * cam.width + px) * 4) = rgba;
@@ -572,8 +615,9 @@ __global__ void k_dequant(const uint8_t *__restrict__ codes, int64_t n, float m,
 hipError_t launch_render(const DevScene &sc, const RenderBatch &rb, float *out, hipStream_t stream) {
     if (rb.total_tiles <= 0) return hipSuccess;
     dim3 grid((unsigned)rb.total_tiles), block(64);
-    if (rb.stats) hipLaunchKernelGGL(k_render<true>, grid, block, 0, stream, sc, rb, out);
-    else hipLaunchKernelGGL(k_render<false>, grid, block, 0, stream, sc, rb, out);
+    auto kern = rb.stats ? (rb.mlp_prec == 0 ? k_render<true, 0> : rb.mlp_prec == 1 ? k_render<true, 1> : k_render<true, 2>)
+                         : (rb.mlp_prec == 0 ? k_render<false, 0> : rb.mlp_prec == 1 ? k_render<false, 1> : k_render<false, 2>);
+    hipLaunchKernelGGL(kern, grid, block, 0, stream, sc, rb, out);
     return hipGetLastError();
 }
 

@@ -229,3 +229,35 @@ def test_full_scene_orbit_views_sampled(torch, merf, full_scene):
     sel = np.concatenate([(c * 480 * 270 + rows[:, None] * 480 + np.arange(480)[None, :]).reshape(-1)
                           for c in range(4)])
     check(gpu[sel], ref, st["fragile"], "orbit views")
+
+
+def psnr(a, b):
+    mse = float(np.mean((a[:, :3] - b[:, :3]) ** 2))
+    return 10.0 * np.log10(1.0 / max(mse, 1e-30))
+
+
+@pytest.mark.parametrize("prec", ["f16", "bf16"])
+def test_precision_mlp_tiny(torch, merf, tiny_scene, tiny_cams, prec):
+    say(f"tiny, deferred MLP in {prec} on MFMA")
+    gpu = gpu_render(torch, merf, tiny_scene, tiny_cams, mlp_prec=prec)
+    ref, st = oracle.render(tiny_scene, tiny_cams)
+    p = psnr(gpu, ref)
+    err = np.abs(gpu - ref)
+    say(f"tiny {prec}: PSNR {p:.2f} dB  max|err| {err.max():.3e}  mean|err| {err.mean():.3e}")
+    assert p >= 45.0
+    # alpha is untouched by the MLP precision
+    f32 = gpu_render(torch, merf, tiny_scene, tiny_cams)
+    assert np.array_equal(gpu[:, 3], f32[:, 3])
+
+
+@pytest.mark.parametrize("prec", ["f16", "bf16"])
+def test_precision_mlp_full_sampled(torch, merf, full_scene, prec):
+    say(f"full 1080p, deferred MLP in {prec} (every 54th row checked)")
+    cams = synth.full_camera()
+    gpu = gpu_render(torch, merf, full_scene, cams, mlp_prec=prec)
+    ref, st = oracle.render(full_scene, cams, rows_stride=54, row_offset=7)
+    rows = np.arange(7, 1080, 54)
+    sel = (rows[:, None] * 1920 + np.arange(1920)[None, :]).reshape(-1)
+    p = psnr(gpu[sel], ref)
+    say(f"full {prec}: PSNR {p:.2f} dB  max|err| {np.abs(gpu[sel] - ref).max():.3e}")
+    assert p >= 45.0
