@@ -15,6 +15,7 @@
 
 #include "merf.h"
 #include "merf_device.h"
+#include "merf_internal.h"
 
 using namespace merf;
 
@@ -26,15 +27,9 @@ struct merf_scene {
     int32_t nbricks;
 };
 
-namespace {
-
-constexpr uint32_t kMagic = 0x4d455246u;  // "MERF"
+namespace merf {
 
 thread_local std::string g_error;
-std::mutex g_mutex;
-std::unordered_set<merf_scene *> g_live;
-size_t g_budget = SIZE_MAX;
-size_t g_in_use = 0;
 
 int fail(int code, const char *fmt, ...) {
     char buf[512];
@@ -49,6 +44,19 @@ int fail(int code, const char *fmt, ...) {
 int hip_fail(hipError_t e, const char *what) {
     return fail(MERF_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
+
+void clear_error() { g_error.clear(); }
+
+}  // namespace merf
+
+namespace {
+
+constexpr uint32_t kMagic = 0x4d455246u;  // "MERF"
+
+std::mutex g_mutex;
+std::unordered_set<merf_scene *> g_live;
+size_t g_budget = SIZE_MAX;
+size_t g_in_use = 0;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -66,8 +74,9 @@ int validate_desc(const merf_scene_desc *d) {
     if (d->channels != kChannels) return fail(MERF_E_INVALID, "channels must be %d (got %d)", kChannels, d->channels);
     if (d->grid_res < 2 * kBlock || d->grid_res % kBlock != 0 || d->grid_res > 4096)
         return fail(MERF_E_INVALID, "grid_res %d must be a multiple of 8 in [16, 4096]", d->grid_res);
-    if (d->plane_res < 2 || d->plane_res > 16384)
-        return fail(MERF_E_INVALID, "plane_res %d must be in [2, 16384]", d->plane_res);
+    // the kernels address every array with 32-bit byte offsets
+    if (d->plane_res < 2 || d->plane_res > 8192)
+        return fail(MERF_E_INVALID, "plane_res %d must be in [2, 8192]", d->plane_res);
     const int64_t nbl = d->grid_res / kBlock;
     if (d->num_blocks < 0 || d->num_blocks > nbl * nbl * nbl)
         return fail(MERF_E_INVALID, "num_blocks %d out of range", d->num_blocks);
@@ -77,8 +86,8 @@ int validate_desc(const merf_scene_desc *d) {
     if (d->occ_levels < 1 || d->occ_levels > MERF_MAX_OCC_LEVELS)
         return fail(MERF_E_INVALID, "occ_levels %d must be in [1, %d]", d->occ_levels, MERF_MAX_OCC_LEVELS);
     for (int l = 0; l < d->occ_levels; ++l) {
-        if (d->occ_res[l] < 1 || d->occ_res[l] > 2048)
-            return fail(MERF_E_INVALID, "occ_res[%d] = %d must be in [1, 2048]", l, d->occ_res[l]);
+        if (d->occ_res[l] < 1 || d->occ_res[l] > 1024)
+            return fail(MERF_E_INVALID, "occ_res[%d] = %d must be in [1, 1024]", l, d->occ_res[l]);
         if (!d->occ[l]) return fail(MERF_E_INVALID, "occ[%d] is NULL", l);
     }
     if (!(d->m_density > 0.0f) || !(d->m_feature > 0.0f) || !std::isfinite(d->m_density) ||
@@ -100,6 +109,48 @@ int validate_desc(const merf_scene_desc *d) {
         }
     }
     return MERF_OK;
+}
+
+// A brick is needed at block position b when any of the 8 blocks b + {0,1}^3
+// is stored.
+int64_t count_bricks(const merf_scene_desc *d) {
+    const int nbl = d->grid_res / kBlock;
+    auto stored = [&](int bx, int by, int bz) {
+        return bx < nbl && by < nbl && bz < nbl && d->block_index[((size_t)bz * nbl + by) * nbl + bx] >= 0;
+    };
+    int64_t n = 0;
+    for (int bz = 0; bz < nbl; ++bz)
+        for (int by = 0; by < nbl; ++by)
+            for (int bx = 0; bx < nbl; ++bx) {
+                bool need = false;
+                for (int dz = 0; dz < 2 && !need; ++dz)
+                    for (int dy = 0; dy < 2 && !need; ++dy)
+                        for (int dx = 0; dx < 2 && !need; ++dx) need = stored(bx + dx, by + dy, bz + dz);
+                n += need ? 1 : 0;
+            }
+    return n;
+}
+
+// Offsets of the arrays inside a scene's single device allocation.
+struct Layout {
+    size_t bidx, bricks, planes, occ[kMaxLevels], mlp, total;
+};
+
+Layout make_layout(const merf_scene_desc *d, int64_t nbricks) {
+    const size_t nbl = (size_t)(d->grid_res / kBlock), R = (size_t)d->plane_res;
+    Layout o{};
+    size_t off = 0;
+    o.bidx = off; off = align_up(off + nbl * nbl * nbl * sizeof(int32_t), 256);
+    o.bricks = off; off = align_up(off + (size_t)(nbricks + 1) * kBrickBytes, 256);
+    o.planes = off; off = align_up(off + 3 * R * R * kChannels, 256);
+    for (int l = 0; l < d->occ_levels; ++l) {
+        const size_t r = (size_t)d->occ_res[l];
+        o.occ[l] = off;
+        off = align_up(off + r * r * r, 256);
+    }
+    o.mlp = off; off = align_up(off + kMlpParams * sizeof(float), 256);
+    o.total = off;
+    return o;
 }
 
 // Bricks with a one-voxel apron: brick (bx, by, bz) holds voxels 8b .. 8b+8 of
@@ -150,9 +201,73 @@ void build_bricks(const merf_scene_desc *d, std::vector<int32_t> &bidx, std::vec
 
 }  // namespace
 
+namespace merf {
+
+const DevScene *scene_dev(merf_scene_t s) { return live(s) ? &s->ds : nullptr; }
+
+size_t scene_device_bytes(const merf_scene_desc *desc) {
+    if (validate_desc(desc) != MERF_OK) return 0;
+    return make_layout(desc, count_bricks(desc)).total;
+}
+
+int check_params(const merf_render_params *p, int R, float *step_out) {
+    if (!p) return fail(MERF_E_INVALID, "render params are NULL");
+    if (p->struct_size != sizeof(merf_render_params))
+        return fail(MERF_E_INVALID, "params struct_size %u != %zu", p->struct_size, sizeof(merf_render_params));
+    const float step = p->step > 0.0f ? p->step : 4.0f / (float)R;
+    if (!std::isfinite(step) || step < 1e-6f) return fail(MERF_E_INVALID, "step %g out of range", (double)p->step);
+    if (!(p->t_min >= 0.0f && p->t_min < 1.0f)) return fail(MERF_E_INVALID, "t_min %g not in [0, 1)", (double)p->t_min);
+    if (p->delta_mode != 0 && p->delta_mode != 1) return fail(MERF_E_INVALID, "delta_mode %d", p->delta_mode);
+    if (p->mlp_prec < 0 || p->mlp_prec > 2) return fail(MERF_E_INVALID, "mlp_prec %d not in {0, 1, 2}", p->mlp_prec);
+    if (p->feat_prec != 0 && p->feat_prec != 1) return fail(MERF_E_INVALID, "feat_prec %d not in {0, 1}", p->feat_prec);
+    *step_out = step;
+    return MERF_OK;
+}
+
+int check_camera(const merf_camera &c, int i) {
+    if (c.width < 1 || c.height < 1 || c.width > 16384 || c.height > 16384)
+        return fail(MERF_E_INVALID, "camera %d: size %dx%d out of range", i, c.width, c.height);
+    bool ok = std::isfinite(c.fx) && std::isfinite(c.fy) && std::isfinite(c.cx) && std::isfinite(c.cy) &&
+              c.fx != 0.0f && c.fy != 0.0f;
+    for (int k = 0; k < 12; ++k) ok = ok && std::isfinite(c.c2w[k]);
+    if (!ok) return fail(MERF_E_INVALID, "camera %d: non-finite or zero intrinsics / pose", i);
+    return MERF_OK;
+}
+
+void begin_batch(RenderBatch &rb, const merf_render_params &p, float step) {
+    std::memset(&rb, 0, sizeof rb);
+    rb.step = step;
+    rb.inv_step = 1.0f / step;
+    rb.t_min = p.t_min;
+    rb.delta_mode = p.delta_mode;
+    rb.mlp_prec = p.mlp_prec;
+    rb.feat_prec = p.feat_prec;
+    rb.stats = reinterpret_cast<unsigned long long *>(p.stats_dev);
+}
+
+bool add_camera(RenderBatch &rb, const merf_camera &c, float *out) {
+    if (rb.n_cams >= kCamsPerLaunch) return false;
+    const int tiles_x = (c.width + kTile - 1) / kTile;
+    const int64_t tiles = (int64_t)rb.total_tiles + (int64_t)tiles_x * ((c.height + kTile - 1) / kTile);
+    if (tiles > INT32_MAX) return false;
+    DevCamera &dc = rb.cams[rb.n_cams++];
+    std::memcpy(dc.c2w, c.c2w, sizeof dc.c2w);
+    dc.fx = c.fx; dc.fy = c.fy; dc.cx = c.cx; dc.cy = c.cy;
+    dc.inv_fx = 1.0f / c.fx;
+    dc.inv_fy = 1.0f / c.fy;
+    dc.width = c.width; dc.height = c.height;
+    dc.tiles_x = tiles_x;
+    dc.tile_start = rb.total_tiles;
+    dc.out = out;
+    rb.total_tiles = (int32_t)tiles;
+    return true;
+}
+
+}  // namespace merf
+
 extern "C" {
 
-const char *merf_last_error(void) { return g_error.c_str(); }
+const char *merf_last_error(void) { return merf::g_error.c_str(); }
 
 int merf_set_hbm_budget(size_t bytes) {
     std::lock_guard<std::mutex> lk(g_mutex);
@@ -168,30 +283,22 @@ size_t merf_hbm_in_use(void) {
 size_t merf_scene_bytes(merf_scene_t s) { return live(s) ? s->dev_bytes : 0; }
 
 int merf_scene_upload(const merf_scene_desc *desc, merf_scene_t *out) {
-    g_error.clear();
+    clear_error();
     if (!out) return fail(MERF_E_INVALID, "output handle pointer is NULL");
     *out = nullptr;
     int rc = validate_desc(desc);
     if (rc) return rc;
 
+    const int64_t nbricks = count_bricks(desc);
+    if ((nbricks + 1) * (int64_t)kBrickBytes >= (int64_t)1 << 31)
+        return fail(MERF_E_INVALID, "%lld bricks exceed the 2 GiB addressed by 32-bit offsets", (long long)nbricks);
     std::vector<int32_t> bidx;
     std::vector<uint8_t> bricks;
     build_bricks(desc, bidx, bricks);
     const int L = desc->grid_res, R = desc->plane_res, nbl = L / kBlock;
-
-    // one device allocation, sub-allocated at 256-byte boundaries
-    size_t off = 0;
-    const size_t o_bidx = off; off = align_up(off + bidx.size() * sizeof(int32_t), 256);
-    const size_t o_bricks = off; off = align_up(off + std::max<size_t>(bricks.size(), 8), 256);
-    const size_t o_planes = off; off = align_up(off + (size_t)3 * R * R * kChannels, 256);
-    size_t o_occ[kMaxLevels] = {0, 0, 0, 0};
-    for (int l = 0; l < desc->occ_levels; ++l) {
-        size_t r = (size_t)desc->occ_res[l];
-        o_occ[l] = off;
-        off = align_up(off + r * r * r, 256);
-    }
-    const size_t o_mlp = off; off = align_up(off + kMlpParams * sizeof(float), 256);
-    const size_t total = off;
+    const Layout lay = make_layout(desc, nbricks);
+    const size_t o_bidx = lay.bidx, o_bricks = lay.bricks, o_planes = lay.planes, o_mlp = lay.mlp, total = lay.total;
+    const size_t *o_occ = lay.occ;
 
     {
         std::lock_guard<std::mutex> lk(g_mutex);
@@ -245,6 +352,7 @@ int merf_scene_upload(const merf_scene_desc *desc, merf_scene_t *out) {
     for (int l = 0; l < kMaxLevels; ++l) {
         ds.occ[l] = l < desc->occ_levels ? dev(o_occ[l]) : nullptr;
         ds.occ_res[l] = l < desc->occ_levels ? desc->occ_res[l] : 1;
+        ds.occ_cell[l] = 4.0f / (float)ds.occ_res[l];
     }
     ds.mlp = reinterpret_cast<const float *>(dev(o_mlp));
     ds.L = L;
@@ -262,7 +370,7 @@ int merf_scene_upload(const merf_scene_desc *desc, merf_scene_t *out) {
 }
 
 int merf_free(merf_scene_t s) {
-    g_error.clear();
+    clear_error();
     {
         std::lock_guard<std::mutex> lk(g_mutex);
         if (!s || !g_live.count(s)) return fail(MERF_E_INVALID, "merf_free: unknown or already freed scene handle");
@@ -283,64 +391,35 @@ int merf_free(merf_scene_t s) {
 
 int merf_render(merf_scene_t s, const merf_camera *cams, int32_t n_cams, const merf_render_params *p,
                 float *out_rgba_dev, void *hip_stream) {
-    g_error.clear();
+    clear_error();
     if (!live(s)) return fail(MERF_E_INVALID, "merf_render: invalid scene handle");
-    if (!p) return fail(MERF_E_INVALID, "merf_render: params is NULL");
-    if (p->struct_size != sizeof(merf_render_params))
-        return fail(MERF_E_INVALID, "params struct_size %u != %zu", p->struct_size, sizeof(merf_render_params));
+    float step = 0.0f;
+    int rc = check_params(p, s->ds.R, &step);
+    if (rc) return rc;
     if (n_cams < 0) return fail(MERF_E_INVALID, "n_cams %d < 0", n_cams);
     if (n_cams == 0) return MERF_OK;
     if (!cams) return fail(MERF_E_INVALID, "cams is NULL");
     if (!out_rgba_dev) return fail(MERF_E_INVALID, "output buffer is NULL");
-    const float step = p->step > 0.0f ? p->step : 4.0f / (float)s->ds.R;
-    if (!std::isfinite(step) || step < 1e-6f) return fail(MERF_E_INVALID, "step %g out of range", (double)p->step);
-    if (!(p->t_min >= 0.0f && p->t_min < 1.0f)) return fail(MERF_E_INVALID, "t_min %g not in [0, 1)", (double)p->t_min);
-    if (p->delta_mode != 0 && p->delta_mode != 1) return fail(MERF_E_INVALID, "delta_mode %d", p->delta_mode);
-    if (p->mlp_prec < 0 || p->mlp_prec > 2) return fail(MERF_E_INVALID, "mlp_prec %d not in {0, 1, 2}", p->mlp_prec);
-    if (p->feat_prec != 0) return fail(MERF_E_INVALID, "feat_prec %d not supported", p->feat_prec);
-    for (int i = 0; i < n_cams; ++i) {
-        const merf_camera &c = cams[i];
-        if (c.width < 1 || c.height < 1 || c.width > 16384 || c.height > 16384)
-            return fail(MERF_E_INVALID, "camera %d: size %dx%d out of range", i, c.width, c.height);
-        bool ok = std::isfinite(c.fx) && std::isfinite(c.fy) && std::isfinite(c.cx) && std::isfinite(c.cy) &&
-                  c.fx != 0.0f && c.fy != 0.0f;
-        for (int k = 0; k < 12; ++k) ok = ok && std::isfinite(c.c2w[k]);
-        if (!ok) return fail(MERF_E_INVALID, "camera %d: non-finite or zero intrinsics / pose", i);
-    }
+    for (int i = 0; i < n_cams; ++i)
+        if ((rc = check_camera(cams[i], i))) return rc;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     int64_t pix = 0;
-    for (int first = 0; first < n_cams; first += kCamsPerLaunch) {
+    for (int first = 0; first < n_cams;) {
         RenderBatch rb;
-        std::memset(&rb, 0, sizeof rb);
-        rb.n_cams = std::min(kCamsPerLaunch, n_cams - first);
-        rb.step = step;
-        rb.t_min = p->t_min;
-        rb.delta_mode = p->delta_mode;
-        rb.mlp_prec = p->mlp_prec;
-        rb.stats = reinterpret_cast<unsigned long long *>(p->stats_dev);
-        int64_t tiles = 0;
-        for (int i = 0; i < rb.n_cams; ++i) {
-            const merf_camera &c = cams[first + i];
-            DevCamera &dc = rb.cams[i];
-            std::memcpy(dc.c2w, c.c2w, sizeof dc.c2w);
-            dc.fx = c.fx; dc.fy = c.fy; dc.cx = c.cx; dc.cy = c.cy;
-            dc.width = c.width; dc.height = c.height;
-            dc.tiles_x = (c.width + kTile - 1) / kTile;
-            dc.tile_start = (int32_t)tiles;
-            dc.pix_start = pix;
-            tiles += (int64_t)dc.tiles_x * ((c.height + kTile - 1) / kTile);
-            pix += (int64_t)c.width * c.height;
+        begin_batch(rb, *p, step);
+        while (first < n_cams && add_camera(rb, cams[first], out_rgba_dev + pix * 4)) {
+            pix += (int64_t)cams[first].width * cams[first].height;
+            ++first;
         }
-        if (tiles > INT32_MAX) return fail(MERF_E_INVALID, "too many pixels in one launch");
-        rb.total_tiles = (int32_t)tiles;
-        hipError_t e = launch_render(s->ds, rb, out_rgba_dev, stream);
+        if (rb.n_cams == 0) return fail(MERF_E_INVALID, "camera %d alone exceeds one launch", first);
+        hipError_t e = launch_render(s->ds, rb, stream);
         if (e != hipSuccess) return hip_fail(e, "render launch");
     }
     return MERF_OK;
 }
 
 int merf_dequantize(const uint8_t *codes_dev, int64_t n, float m, int32_t prec, void *out_dev, void *hip_stream) {
-    g_error.clear();
+    clear_error();
     if (n < 0) return fail(MERF_E_INVALID, "n %lld < 0", (long long)n);
     if (n == 0) return MERF_OK;
     if (!codes_dev || !out_dev) return fail(MERF_E_INVALID, "NULL buffer");

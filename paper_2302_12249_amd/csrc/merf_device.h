@@ -37,26 +37,32 @@ struct DevScene {
     const float *mlp;
     int32_t L, R, nbl, occ_levels;
     int32_t occ_res[kMaxLevels];
+    float occ_cell[kMaxLevels];                  // cell edge 4 / r of each level
     float m_density, m_feature;
 };
 
 struct DevCamera {
     float c2w[12];
     float fx, fy, cx, cy;
+    float inv_fx, inv_fy;
     int32_t width, height, tiles_x, tile_start;  // tile_start: first tile of this camera in the launch
-    int64_t pix_start;                           // first output pixel of this camera
+    float *out;                                  // device RGBA of this camera's first pixel (row-major)
 };
 
 struct RenderBatch {
     int32_t n_cams, total_tiles;
-    float step, t_min;
-    int32_t delta_mode, mlp_prec;
+    float step, inv_step, t_min;
+    int32_t delta_mode, mlp_prec, feat_prec;
     unsigned long long *stats;
     DevCamera cams[kCamsPerLaunch];
 };
 
 // Launchers (merf_render.hip).
-hipError_t launch_render(const DevScene &sc, const RenderBatch &rb, float *out, hipStream_t stream);
+hipError_t launch_render(const DevScene &sc, const RenderBatch &rb, hipStream_t stream);
+// The kernel a batch runs and its launch shape (for graph nodes).
+const void *render_kernel(const RenderBatch &rb);
+dim3 render_grid(const RenderBatch &rb);
+constexpr int kRenderBlock = 64;
 hipError_t launch_dequant(const uint8_t *codes, int64_t n, float m, int prec, void *out, hipStream_t stream);
 
 }  // namespace merf

@@ -1,0 +1,35 @@
+// merf_internal.h -- host helpers shared by the C ABI (merf_api.hip) and the
+// serving runtime (merf_serve.hip).  Not part of the public interface.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "merf.h"
+#include "merf_device.h"
+
+namespace merf {
+
+// Record the calling thread's error message; returns code.
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+void clear_error();
+
+// Device view of a live scene handle, or nullptr.
+const DevScene *scene_dev(merf_scene_t s);
+
+// Device bytes merf_scene_upload would allocate for desc (0 if desc is invalid).
+size_t scene_device_bytes(const merf_scene_desc *desc);
+
+// Validate render parameters for a scene of plane resolution R; on success
+// stores the effective contracted step.
+int check_params(const merf_render_params *p, int R, float *step);
+int check_camera(const merf_camera &c, int index);
+
+// Start a launch descriptor (no cameras yet) / append one camera whose
+// row-major RGBA pixels start at out.  add_camera fails when the launch is
+// full or its tile count would overflow.
+void begin_batch(RenderBatch &rb, const merf_render_params &p, float step);
+bool add_camera(RenderBatch &rb, const merf_camera &c, float *out);
+
+}  // namespace merf

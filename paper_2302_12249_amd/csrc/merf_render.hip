@@ -51,7 +51,17 @@ __device__ __forceinline__ float deq_f32(uint32_t b, float m2, float m255) {
     return fmaf(r, kRcp255, q);
 }
 
+// Eq. 8 to float16: RN16(RN32(b * RN32(2m/255) - m)) equals the correctly
+// rounded float16 of the exact 2mb/255 - m for every code and m in {7, 14}
+// (checked exhaustively by the test-suite); returned widened to float.
+__device__ __forceinline__ float deq_f16(uint32_t b, float a, float m) {
+    return (float)(_Float16)fmaf((float)b, a, -m);
+}
+
 __device__ __forceinline__ uint32_t byte_of(uint32_t w, int i) { return (w >> (8 * i)) & 0xffu; }
+
+// Hardware reciprocal (v_rcp_f32, 1 ulp); rcp(+-0) = +-inf.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // ---------------------------------------------------------------------------
 // Eq. 7 regions: 0 = unit cube, 1 + 2j + (x_j < 0) = outer region of axis j.
@@ -73,8 +83,7 @@ __device__ __forceinline__ float3 map_region(int reg, float3 x) {
     int j = (reg - 1) >> 1;
     float s = ((reg - 1) & 1) ? -1.0f : 1.0f;
     float xj = j == 0 ? x.x : (j == 1 ? x.y : x.z);
-    float a = fabsf(xj);
-    float ia = 1.0f / a;
+    float ia = rcp(fabsf(xj));
     float3 y = make_float3(x.x * ia, x.y * ia, x.z * ia);
     float yj = (2.0f - ia) * s;
     if (j == 0) y.x = yj; else if (j == 1) y.y = yj; else y.z = yj;
@@ -86,7 +95,7 @@ __device__ __forceinline__ float3 limit_point(int reg, float3 d) {
     int j = (reg - 1) >> 1;
     float s = ((reg - 1) & 1) ? -1.0f : 1.0f;
     float dj = j == 0 ? d.x : (j == 1 ? d.y : d.z);
-    float ia = 1.0f / fabsf(dj);
+    float ia = rcp(fabsf(dj));
     float3 y = make_float3(d.x * ia, d.y * ia, d.z * ia);
     if (j == 0) y.x = 2.0f * s; else if (j == 1) y.y = 2.0f * s; else y.z = 2.0f * s;
     return y;
@@ -98,7 +107,7 @@ __device__ __forceinline__ float3 unmap_region(int reg, float3 y) {
     int j = (reg - 1) >> 1;
     float s = ((reg - 1) & 1) ? -1.0f : 1.0f;
     float yj = j == 0 ? y.x : (j == 1 ? y.y : y.z);
-    float a = 1.0f / (2.0f - s * yj);
+    float a = rcp(2.0f - s * yj);
     float3 x = make_float3(y.x * a, y.y * a, y.z * a);
     if (j == 0) x.x = s * a; else if (j == 1) x.y = s * a; else x.z = s * a;
     return x;
@@ -111,20 +120,23 @@ struct Candidates {
 __device__ __forceinline__ float valid_t(float t) { return (t > 0.0f && t < kInf) ? t : kInf; }
 
 // Parameters t > 0 where the ray can change region: x_j = +-1, x_j = +-x_k.
+// Hardware reciprocals (1 ulp) replace divisions: a breakpoint is only needed
+// to FP32 accuracy, and a zero denominator still gives +-inf (no candidate).
 __device__ __forceinline__ Candidates make_candidates(float3 o, float3 d) {
     Candidates C;
-    C.c[0] = valid_t((1.0f - o.x) / d.x);
-    C.c[1] = valid_t((-1.0f - o.x) / d.x);
-    C.c[2] = valid_t((1.0f - o.y) / d.y);
-    C.c[3] = valid_t((-1.0f - o.y) / d.y);
-    C.c[4] = valid_t((1.0f - o.z) / d.z);
-    C.c[5] = valid_t((-1.0f - o.z) / d.z);
-    C.c[6] = valid_t((o.y - o.x) / (d.x - d.y));
-    C.c[7] = valid_t((-o.y - o.x) / (d.x + d.y));
-    C.c[8] = valid_t((o.z - o.x) / (d.x - d.z));
-    C.c[9] = valid_t((-o.z - o.x) / (d.x + d.z));
-    C.c[10] = valid_t((o.z - o.y) / (d.y - d.z));
-    C.c[11] = valid_t((-o.z - o.y) / (d.y + d.z));
+    const float ix = rcp(d.x), iy = rcp(d.y), iz = rcp(d.z);
+    C.c[0] = valid_t((1.0f - o.x) * ix);
+    C.c[1] = valid_t((-1.0f - o.x) * ix);
+    C.c[2] = valid_t((1.0f - o.y) * iy);
+    C.c[3] = valid_t((-1.0f - o.y) * iy);
+    C.c[4] = valid_t((1.0f - o.z) * iz);
+    C.c[5] = valid_t((-1.0f - o.z) * iz);
+    C.c[6] = valid_t((o.y - o.x) * rcp(d.x - d.y));
+    C.c[7] = valid_t((-o.y - o.x) * rcp(d.x + d.y));
+    C.c[8] = valid_t((o.z - o.x) * rcp(d.x - d.z));
+    C.c[9] = valid_t((-o.z - o.x) * rcp(d.x + d.z));
+    C.c[10] = valid_t((o.z - o.y) * rcp(d.y - d.z));
+    C.c[11] = valid_t((-o.z - o.y) * rcp(d.y + d.z));
     return C;
 }
 
@@ -142,7 +154,7 @@ __device__ __forceinline__ int region_at(float3 o, float3 d, float t) {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-__device__ __forceinline__ float sigmoid(float x) { return 1.0f / (1.0f + __expf(-x)); }
+__device__ __forceinline__ float sigmoid(float x) { return __builtin_amdgcn_rcpf(1.0f + __expf(-x)); }
 
 // XCD-aware tile order: consecutive workgroups are dispatched round-robin over
 // the 8 XCDs, so give each XCD a contiguous run of tiles (neighbouring tiles
@@ -181,7 +193,7 @@ __device__ __forceinline__ u32x4 load_pair(const uint8_t *base, uint32_t off) {
 // One evaluated sample: gather, dequantise, decode, composite.
 // All offsets are 32-bit (the upload keeps every array below 2 GiB) and are
 // added to uniform base pointers, so no 64-bit address arithmetic runs per lane.
-template <bool kStats>
+template <bool kStats, bool kFeatF16>
 __device__ __forceinline__ void shade_sample(const DevScene &sc, float3 p, float delta, Accum &acc, Counters &cnt) {
     // ---- three planes: bilinear.  Their addresses depend on no load, so they
     // are issued first and overlap the brick-index round trip below.
@@ -247,16 +259,26 @@ __device__ __forceinline__ void shade_sample(const DevScene &sc, float3 p, float
     }
     // ---- Eq. 8 dequantises each code affinely, q(b) = a b - m with a = 2m/255,
     // and the 20 weights form four partitions of unity (one per source), so
-    // sum_i w_i q(b_i) = a * sum_i w_i b_i - 4m exactly.  Interpolating the
-    // codes and applying the affine map once per channel computes the same
-    // real number with one convert and one FMA per texel and channel; the two
-    // FP32 evaluations differ by rounding only (below 1e-6 relative).
+    // sum_i w_i q(b_i) = a * sum_i w_i b_i - 4m exactly.  The FP32 path
+    // (kFeatF16 = false) interpolates the codes and applies the affine map
+    // once per channel: the same real number with one convert and one FMA per
+    // texel and channel; the two FP32 evaluations differ by rounding only
+    // (below 1e-6 relative).  The FP16 path dequantises every code to its
+    // correctly rounded float16 value first (deq_f16) and interpolates those
+    // values with FP32 weights and FP32 sums.
+    const float md = sc.m_density, mf = sc.m_feature;
     // ---- density first (Sec. 6): appearance is read only when alpha != 0
     float s0 = 0.0f;
+    if constexpr (kFeatF16) {
+        const float ad = md * (2.0f / 255.0f);
 #pragma unroll
-    for (int i = 0; i < 20; ++i) s0 = fmaf(w[i], (float)byte_of(lo[i], 0), s0);
-    const float md = sc.m_density, mf = sc.m_feature;
-    float tau = __expf(fmaf(s0, md * (2.0f / 255.0f), -4.0f * md));   // Eq. 6
+        for (int i = 0; i < 20; ++i) s0 = fmaf(w[i], deq_f16(byte_of(lo[i], 0), ad, md), s0);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 20; ++i) s0 = fmaf(w[i], (float)byte_of(lo[i], 0), s0);
+        s0 = fmaf(s0, md * (2.0f / 255.0f), -4.0f * md);
+    }
+    float tau = __expf(s0);                       // Eq. 6
     float trans = __expf(-tau * delta);           // e^{-tau delta} = 1 - alpha (Eq. 1)
     float alpha = 1.0f - trans;
     if (kStats) ++cnt.evaluated;
@@ -265,16 +287,26 @@ __device__ __forceinline__ void shade_sample(const DevScene &sc, float3 p, float
         float s[7];
 #pragma unroll
         for (int c = 0; c < 7; ++c) s[c] = 0.0f;
+        const float af = mf * (2.0f / 255.0f);
+        if constexpr (kFeatF16) {
 #pragma unroll
-        for (int i = 0; i < 20; ++i) {
+            for (int i = 0; i < 20; ++i) {
 #pragma unroll
-            for (int c = 1; c < 4; ++c) s[c - 1] = fmaf(w[i], (float)byte_of(lo[i], c), s[c - 1]);
+                for (int c = 1; c < 4; ++c) s[c - 1] = fmaf(w[i], deq_f16(byte_of(lo[i], c), af, mf), s[c - 1]);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) s[3 + c] = fmaf(w[i], (float)byte_of(hi[i], c), s[3 + c]);
+                for (int c = 0; c < 4; ++c) s[3 + c] = fmaf(w[i], deq_f16(byte_of(hi[i], c), af, mf), s[3 + c]);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 20; ++i) {
+#pragma unroll
+                for (int c = 1; c < 4; ++c) s[c - 1] = fmaf(w[i], (float)byte_of(lo[i], c), s[c - 1]);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) s[3 + c] = fmaf(w[i], (float)byte_of(hi[i], c), s[3 + c]);
+            }
+#pragma unroll
+            for (int c = 0; c < 7; ++c) s[c] = fmaf(s[c], af, -4.0f * mf);
         }
-        const float af = mf * (2.0f / 255.0f), bf = -4.0f * mf;
-#pragma unroll
-        for (int c = 0; c < 7; ++c) s[c] = fmaf(s[c], af, bf);
         float wt = acc.T * alpha;                 // Eq. 1-2
         acc.cd0 = fmaf(wt, sigmoid(s[0]), acc.cd0);
         acc.cd1 = fmaf(wt, sigmoid(s[1]), acc.cd1);
@@ -298,7 +330,7 @@ struct Segment {
 
 // Set up the segment of the ray that starts at world parameter ta in region
 // reg: find where the region next changes (Eq. 7 breakpoints), map both ends.
-__device__ __forceinline__ void open_segment(float3 o, float3 d, float ta, int reg, float step, Segment &s) {
+__device__ __forceinline__ void open_segment(float3 o, float3 d, float ta, int reg, float istep, Segment &s) {
     const Candidates C = make_candidates(o, d);
     float tb = kInf, cur = ta;
     int reg_next = reg;
@@ -327,14 +359,14 @@ __device__ __forceinline__ void open_segment(float3 o, float3 d, float ta, int r
         s.len = 0.0f;
         return;
     }
-    float il = 1.0f / len;
+    float il = rcp(len);
     e.x *= il; e.y *= il; e.z *= il;
     s.e = e;
     s.len = len;
-    s.n = (int)ceilf(len / step);
-    s.iex = e.x != 0.0f ? 1.0f / e.x : 0.0f;
-    s.iey = e.y != 0.0f ? 1.0f / e.y : 0.0f;
-    s.iez = e.z != 0.0f ? 1.0f / e.z : 0.0f;
+    s.n = (int)ceilf(len * istep);
+    s.iex = e.x != 0.0f ? rcp(e.x) : 0.0f;
+    s.iey = e.y != 0.0f ? rcp(e.y) : 0.0f;
+    s.iez = e.z != 0.0f ? rcp(e.z) : 0.0f;
 }
 
 // Deferred MLP (Eq. 3, App. B) for the 64 pixels of a wave on the matrix
@@ -350,7 +382,11 @@ __device__ __forceinline__ void open_segment(float3 o, float3 d, float ta, int r
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef _Float16 halfx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-constexpr int kXStride = 37;      // LDS row stride (floats) of the 36-wide padded input
+// LDS row of one pixel: the 34 inputs zero-padded to 48 (three K = 16 steps
+// of the half-precision products read up to index 47); odd stride, so the 16
+// rows read by one instruction fall in different banks.
+constexpr int kXWidth = 48;
+constexpr int kXStride = kXWidth + 1;
 
 __device__ __forceinline__ void mlp_encode(float *x, const Accum &acc, float3 d) {
     x[0] = acc.cd0; x[1] = acc.cd1; x[2] = acc.cd2;
@@ -362,8 +398,8 @@ __device__ __forceinline__ void mlp_encode(float *x, const Accum &acc, float3 d)
         x[10 + 3 * k] = __sinf(d.x * sc); x[11 + 3 * k] = __sinf(d.y * sc); x[12 + 3 * k] = __sinf(d.z * sc);
         x[22 + 3 * k] = __cosf(d.x * sc); x[23 + 3 * k] = __cosf(d.y * sc); x[24 + 3 * k] = __cosf(d.z * sc);
     }
-    x[34] = 0.0f;
-    x[35] = 0.0f;
+#pragma unroll
+    for (int k = kMlpIn; k < kXWidth; ++k) x[k] = 0.0f;
 }
 
 // 16x16 block product with K = 16 in half precision: lane l supplies
@@ -389,10 +425,10 @@ __device__ __forceinline__ float3 deferred_mlp_mfma(const float *__restrict__ W,
     const float *W0 = W, *b0 = W0 + kMlpIn * kMlpHidden, *W1 = b0 + kMlpHidden, *b1 = W1 + kMlpHidden * kMlpHidden,
                 *W2 = b1 + kMlpHidden, *b2 = W2 + kMlpHidden * kMlpOut;
     {
-        float x[36];
+        float x[kXWidth];
         mlp_encode(x, acc, d);
 #pragma unroll
-        for (int i = 0; i < 36; ++i) xs[lane * kXStride + i] = x[i];
+        for (int i = 0; i < kXWidth; ++i) xs[lane * kXStride + i] = x[i];
     }
     // layer-1 A operand W0^T[hidden j][k]: fp32 steps take k = 9g + q,
     // half-precision steps k = 16 (q / 4) + 4g + q % 4 (zero past 34)
@@ -454,8 +490,8 @@ __device__ __forceinline__ float3 deferred_mlp_mfma(const float *__restrict__ W,
     return make_float3(xs[lane * kXStride + 0], xs[lane * kXStride + 1], xs[lane * kXStride + 2]);
 }
 
-template <bool kStats, int kMlpPrec>
-__global__ __launch_bounds__(64) void k_render(const DevScene sc, const RenderBatch rb, float *__restrict__ out) {
+template <bool kStats, int kMlpPrec, bool kFeatF16>
+__global__ __launch_bounds__(64) void k_render(const DevScene sc, const RenderBatch rb) {
     __shared__ float xs[64 * kXStride];
     const int tile = xcd_remap((int)blockIdx.x, rb.total_tiles);
     int c = 0;
@@ -470,26 +506,27 @@ __global__ __launch_bounds__(64) void k_render(const DevScene sc, const RenderBa
     const bool active = px < cam.width && py < cam.height;
 
     // ---- pinhole ray
-    float vx = ((float)px + 0.5f - cam.cx) / cam.fx;
-    float vy = ((float)py + 0.5f - cam.cy) / cam.fy;
+    float vx = ((float)px + 0.5f - cam.cx) * cam.inv_fx;
+    float vy = ((float)py + 0.5f - cam.cy) * cam.inv_fy;
     float3 d = make_float3(fmaf(cam.c2w[0], vx, fmaf(cam.c2w[1], vy, cam.c2w[2])),
                            fmaf(cam.c2w[4], vx, fmaf(cam.c2w[5], vy, cam.c2w[6])),
                            fmaf(cam.c2w[8], vx, fmaf(cam.c2w[9], vy, cam.c2w[10])));
-    float inv = 1.0f / sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
+    float inv = __builtin_amdgcn_rsqf(d.x * d.x + d.y * d.y + d.z * d.z);
     d.x *= inv; d.y *= inv; d.z *= inv;
     const float3 o = make_float3(cam.c2w[3], cam.c2w[7], cam.c2w[11]);
 
     Counters cnt = {0u, 0u, 0u, 0u};
     Accum acc = {1.0f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    const float step = rb.step, istep = 1.0f / step;
+    const float step = rb.step, istep = rb.inv_step;
     Segment s;
     {
         const Candidates C = make_candidates(o, d);
         const float c1 = next_candidate(C, 0.0f);
-        open_segment(o, d, 0.0f, region_at(o, d, c1 < kInf ? 0.5f * c1 : 1.0f), step, s);
+        open_segment(o, d, 0.0f, region_at(o, d, c1 < kInf ? 0.5f * c1 : 1.0f), istep, s);
     }
     int nseg = 1;
     bool alive = active, terminated = false;
+    float known[kMaxLevels] = {0.0f, 0.0f, 0.0f, 0.0f};   // per level: occupied up to this u
 
     // Each round: every live lane advances to its next occupied sample (cheap
     // skip iterations), then all lanes that found one shade it together, so
@@ -503,8 +540,9 @@ __global__ __launch_bounds__(64) void k_render(const DevScene sc, const RenderBa
             if (s.k >= s.n) {
                 // segment done: continue in the next region, if any
                 if (!(s.tb < kInf) || nseg >= 8) { alive = false; break; }
-                open_segment(o, d, s.tb, s.reg_next, step, s);
+                open_segment(o, d, s.tb, s.reg_next, istep, s);
                 ++nseg;
+                known[0] = known[1] = known[2] = known[3] = 0.0f;
                 continue;
             }
             const float u0 = (float)s.k * step;
@@ -512,19 +550,35 @@ __global__ __launch_bounds__(64) void k_render(const DevScene sc, const RenderBa
             const float um = 0.5f * (u0 + u1);
             p = make_float3(fmaf(um, s.e.x, s.A.x), fmaf(um, s.e.y, s.A.y), fmaf(um, s.e.z, s.A.z));
             if (kStats) ++cnt.visited;
-            // occupancy, coarse to fine: stop at the first empty level
-            int empty = -1, cx = 0, cy = 0, cz = 0, r = 1;
+            // occupancy, coarse to fine: stop at the first empty level.  A cell
+            // seen occupied stays known until the segment leaves it (its exit
+            // minus the guard), so later samples inside it need no lookup.
+            int empty = -1;
+            float uexit = 0.0f;
 #pragma unroll
             for (int l = 0; l < kMaxLevels; ++l) {
-                if (l < sc.occ_levels && empty < 0) {
+                if (l < sc.occ_levels && empty < 0 && !(um < known[l])) {
                     const int rl = sc.occ_res[l];
                     const float os = (float)rl * 0.25f;
-                    int qx = clampi((int)floorf((p.x + 2.0f) * os), 0, rl - 1);
-                    int qy = clampi((int)floorf((p.y + 2.0f) * os), 0, rl - 1);
-                    int qz = clampi((int)floorf((p.z + 2.0f) * os), 0, rl - 1);
+                    const int qx = clampi((int)floorf((p.x + 2.0f) * os), 0, rl - 1);
+                    const int qy = clampi((int)floorf((p.y + 2.0f) * os), 0, rl - 1);
+                    const int qz = clampi((int)floorf((p.z + 2.0f) * os), 0, rl - 1);
                     if (kStats) ++cnt.occ_lookups;
-                    if (!sc.occ[l][((uint32_t)qz * rl + qy) * rl + qx]) {
-                        empty = l; cx = qx; cy = qy; cz = qz; r = rl;
+                    const bool occ = sc.occ[l][((uint32_t)qz * rl + qy) * rl + qx] != 0;
+                    // exit parameter of this cell along the segment (slab test)
+                    const float h = sc.occ_cell[l];
+                    const float bx = (float)(s.e.x > 0.0f ? qx + 1 : qx) * h - 2.0f;
+                    const float by = (float)(s.e.y > 0.0f ? qy + 1 : qy) * h - 2.0f;
+                    const float bz = (float)(s.e.z > 0.0f ? qz + 1 : qz) * h - 2.0f;
+                    const float tx = s.e.x != 0.0f ? (bx - s.A.x) * s.iex : kInf;
+                    const float ty = s.e.y != 0.0f ? (by - s.A.y) * s.iey : kInf;
+                    const float tz = s.e.z != 0.0f ? (bz - s.A.z) * s.iez : kInf;
+                    const float ue = fminf(tx, fminf(ty, tz));
+                    if (occ) {
+                        known[l] = ue - kSkipGuard;
+                    } else {
+                        empty = l;
+                        uexit = ue;
                     }
                 }
             }
@@ -553,22 +607,14 @@ __global__ __launch_bounds__(64) void k_render(const DevScene sc, const RenderBa
                 }
                 break;
             }
-            // leave the empty cell: exit parameter along the segment (slab test)
-            const float h = 4.0f / (float)r;
-            float bx = (s.e.x > 0.0f ? (float)(cx + 1) : (float)cx) * h - 2.0f;
-            float by = (s.e.y > 0.0f ? (float)(cy + 1) : (float)cy) * h - 2.0f;
-            float bz = (s.e.z > 0.0f ? (float)(cz + 1) : (float)cz) * h - 2.0f;
-            float tx = s.e.x != 0.0f ? (bx - s.A.x) * s.iex : kInf;
-            float ty = s.e.y != 0.0f ? (by - s.A.y) * s.iey : kInf;
-            float tz = s.e.z != 0.0f ? (bz - s.A.z) * s.iez : kInf;
-            float uexit = fminf(tx, fminf(ty, tz));
+            // leave the empty cell
             // first lattice interval whose midpoint lies past the exit
             float kn = floorf((uexit - kSkipGuard) * istep - 0.5f) + 1.0f;
             int knext = kn > (float)s.n ? s.n : (int)fmaxf(kn, 0.0f);
             s.k = max(s.k + 1, knext);
         }
         if (found) {
-            shade_sample<kStats>(sc, p, delta, acc, cnt);
+            shade_sample<kStats, kFeatF16>(sc, p, delta, acc, cnt);
             ++s.k;
             if (acc.T < rb.t_min) {          // early termination (Sec. 6)
                 alive = false;
@@ -580,7 +626,7 @@ __global__ __launch_bounds__(64) void k_render(const DevScene sc, const RenderBa
     const float3 h = deferred_mlp_mfma<kMlpPrec>(sc.mlp, xs, acc, d);
     if (active) {
         float4 rgba = make_float4(acc.cd0 + h.x, acc.cd1 + h.y, acc.cd2 + h.z, 1.0f - acc.T);
-        *reinterpret_cast<float4 *>(out + (cam.pix_start + (int64_t)py * cam.width + px) * 4) = rgba;
+        *reinterpret_cast<float4 *>(cam.out + ((int64_t)py * cam.width + px) * 4) = rgba;
     }
     if (kStats) {
         unsigned long long v[6] = {active ? 1ull : 0ull, cnt.occ_lookups, cnt.visited, cnt.evaluated, cnt.contributing,
@@ -612,13 +658,23 @@ __global__ void k_dequant(const uint8_t *__restrict__ codes, int64_t n, float m,
 
 }  // namespace
 
-hipError_t launch_render(const DevScene &sc, const RenderBatch &rb, float *out, hipStream_t stream) {
+template <bool kStats, bool kFeatF16>
+const void *render_kernel_mlp(int mlp_prec) {
+    return mlp_prec == 0 ? (const void *)k_render<kStats, 0, kFeatF16>
+         : mlp_prec == 1 ? (const void *)k_render<kStats, 1, kFeatF16> : (const void *)k_render<kStats, 2, kFeatF16>;
+}
+
+const void *render_kernel(const RenderBatch &rb) {
+    if (rb.stats) return rb.feat_prec ? render_kernel_mlp<true, true>(rb.mlp_prec) : render_kernel_mlp<true, false>(rb.mlp_prec);
+    return rb.feat_prec ? render_kernel_mlp<false, true>(rb.mlp_prec) : render_kernel_mlp<false, false>(rb.mlp_prec);
+}
+
+dim3 render_grid(const RenderBatch &rb) { return dim3((unsigned)rb.total_tiles); }
+
+hipError_t launch_render(const DevScene &sc, const RenderBatch &rb, hipStream_t stream) {
     if (rb.total_tiles <= 0) return hipSuccess;
-    dim3 grid((unsigned)rb.total_tiles), block(64);
-    auto kern = rb.stats ? (rb.mlp_prec == 0 ? k_render<true, 0> : rb.mlp_prec == 1 ? k_render<true, 1> : k_render<true, 2>)
-                         : (rb.mlp_prec == 0 ? k_render<false, 0> : rb.mlp_prec == 1 ? k_render<false, 1> : k_render<false, 2>);
-    hipLaunchKernelGGL(kern, grid, block, 0, stream, sc, rb, out);
-    return hipGetLastError();
+    void *args[] = {const_cast<DevScene *>(&sc), const_cast<RenderBatch *>(&rb)};
+    return hipLaunchKernel(render_kernel(rb), render_grid(rb), dim3(kRenderBlock), args, 0, stream);
 }
 
 hipError_t launch_dequant(const uint8_t *codes, int64_t n, float m, int prec, void *out, hipStream_t stream) {

@@ -222,3 +222,113 @@ class Renderer:
         p = render_params(stats_ptr=stats.data_ptr() if stats is not None else None, **kw)
         merf_render(self.handle, camera_array(cams), len(cams), p, out.data_ptr(), st.cuda_stream)
         return out
+
+
+# ---------------------------------------------------------------------------
+# serving runtime (include/merf_serve.h)
+# ---------------------------------------------------------------------------
+
+class merf_server_config(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("slots", C.c_int32), ("max_batch", C.c_int32),
+                ("use_graphs", C.c_int32), ("evict_idle", C.c_int32), ("pad", C.c_int32),
+                ("hbm_budget", C.c_size_t)]
+
+
+class merf_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("launches", C.c_uint64),
+                ("graph_launches", C.c_uint64), ("evictions", C.c_uint64), ("resident_bytes", C.c_size_t),
+                ("resident_scenes", C.c_int32), ("max_inflight", C.c_int32)]
+
+
+SERVE_EXPORTS = ["merf_server_create", "merf_server_destroy", "merf_server_add_scene", "merf_server_remove_scene",
+                 "merf_server_submit", "merf_server_poll", "merf_server_wait", "merf_server_drain",
+                 "merf_server_get_stats"]
+
+
+def _serve_lib():
+    lib = load()
+    if getattr(lib, "_serve_ready", False):
+        return lib
+    vp, i32, u64 = C.c_void_p, C.c_int32, C.c_uint64
+    lib.merf_server_create.argtypes = [C.POINTER(merf_server_config), C.POINTER(vp)]
+    lib.merf_server_destroy.argtypes = [vp]
+    lib.merf_server_add_scene.argtypes = [vp, C.POINTER(merf_scene_desc), C.POINTER(i32)]
+    lib.merf_server_remove_scene.argtypes = [vp, i32]
+    lib.merf_server_submit.argtypes = [vp, i32, C.POINTER(merf_camera), C.POINTER(merf_render_params), vp,
+                                       C.POINTER(u64)]
+    lib.merf_server_poll.argtypes = [vp, u64]
+    lib.merf_server_wait.argtypes = [vp, u64, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.merf_server_drain.argtypes = [vp]
+    lib.merf_server_get_stats.argtypes = [vp, C.POINTER(merf_server_stats)]
+    for n in SERVE_EXPORTS:
+        getattr(lib, n).restype = C.c_int
+    lib._serve_ready = True
+    return lib
+
+
+def server_config(slots=4, max_batch=16, use_graphs=True, evict_idle=False, hbm_budget=0) -> merf_server_config:
+    c = merf_server_config()
+    c.struct_size = C.sizeof(merf_server_config)
+    c.slots, c.max_batch, c.use_graphs, c.evict_idle = int(slots), int(max_batch), int(bool(use_graphs)), int(bool(evict_idle))
+    c.hbm_budget = int(hbm_budget)
+    return c
+
+
+class Server:
+    """Resident scenes + continuous batching of single-view requests."""
+
+    def __init__(self, **cfg):
+        self.lib = _serve_lib()
+        h = C.c_void_p()
+        c = server_config(**cfg)
+        _check(self.lib.merf_server_create(C.byref(c), C.byref(h)))
+        self.h = h.value
+
+    def close(self):
+        if self.h:
+            rc = self.lib.merf_server_destroy(C.c_void_p(self.h))
+            self.h = None
+            _check(rc)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_scene(self, scene) -> int:
+        d, keep = scene_desc(scene)
+        sid = C.c_int32()
+        _check(self.lib.merf_server_add_scene(C.c_void_p(self.h), C.byref(d), C.byref(sid)))
+        del keep
+        return sid.value
+
+    def remove_scene(self, sid: int):
+        _check(self.lib.merf_server_remove_scene(C.c_void_p(self.h), int(sid)))
+
+    def submit(self, sid: int, cam_arr, index: int, out_ptr: int, params: merf_render_params) -> int:
+        """Queue camera cam_arr[index] (from camera_array) of scene sid into device memory out_ptr."""
+        t = C.c_uint64()
+        _check(self.lib.merf_server_submit(C.c_void_p(self.h), int(sid), C.byref(cam_arr[index]), C.byref(params),
+                                           C.c_void_p(out_ptr), C.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        rc = self.lib.merf_server_poll(C.c_void_p(self.h), C.c_uint64(ticket))
+        if rc < 0:
+            _check(rc)
+        return rc == 1
+
+    def wait(self, ticket: int):
+        """Block until done; returns (latency_ms, queue_ms)."""
+        lat, q = C.c_double(), C.c_double()
+        _check(self.lib.merf_server_wait(C.c_void_p(self.h), C.c_uint64(ticket), C.byref(lat), C.byref(q)))
+        return lat.value, q.value
+
+    def drain(self):
+        _check(self.lib.merf_server_drain(C.c_void_p(self.h)))
+
+    def stats(self) -> dict:
+        s = merf_server_stats()
+        _check(self.lib.merf_server_get_stats(C.c_void_p(self.h), C.byref(s)))
+        return {n: getattr(s, n) for n, _ in merf_server_stats._fields_}

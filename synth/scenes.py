@@ -138,7 +138,8 @@ def maxpool(a: np.ndarray, f: int) -> np.ndarray:
 
 
 def _mark_sphere(occ: np.ndarray, center: np.ndarray, rad: float, extent: float,
-                 reach: np.ndarray) -> None:
+                 reach: np.ndarray):
+    """Mark the cells meeting the sphere; returns the touched index box (lo, hi) per axis (x, y, z)."""
     res = occ.shape[0]
     h = 4.0 / res
     lo_i = np.clip(np.floor((center - rad + 2.0) / h).astype(int), 0, res - 1)
@@ -156,30 +157,46 @@ def _mark_sphere(occ: np.ndarray, center: np.ndarray, rad: float, extent: float,
     hit = (d2 <= rad * rad) & ez[:, None, None] & ey[None, :, None] & ex[None, None, :]
     sub = np.ix_(iz, iy, ix)
     occ[sub] |= (hit & reach[sub]).astype(np.uint8)
+    return lo_i, hi_i
 
 
 def draw_occupancy(L: int, target_block_frac: float, extent: float, r_lo: float, r_hi: float,
                    rng: np.random.Generator, max_spheres: int = 100000) -> Tuple[np.ndarray, int]:
     """Add random spheres until the block-mask occupancy reaches the target.
 
-    Returns the finest occupancy level (resolution L/4, uint8 0/1) and the
-    number of spheres drawn.
+    The block count is checked after every sphere for small targets and after
+    every 8th sphere otherwise.  Returns the finest occupancy level
+    (resolution L/4, uint8 0/1) and the number of spheres drawn.
     """
     rf = L // 4
     nb = L // BLOCK
     occ = np.zeros((rf, rf, rf), np.uint8)
+    blocks = np.zeros((nb, nb, nb), np.uint8)     # max-pool x2 of occ, kept up to date
+    count = 0
     reach = reachable_mask(rf)
     target = target_block_frac * nb ** 3
     n = 0
     while n < max_spheres:
         center = rng.uniform(-extent, extent, 3)
         rad = rng.uniform(r_lo, r_hi)
-        _mark_sphere(occ, center, rad, extent, reach)
+        lo_i, hi_i = _mark_sphere(occ, center, rad, extent, reach)
+        b0, b1 = lo_i // 2, hi_i // 2 + 1           # touched blocks, (x, y, z)
+        sub = occ[2 * b0[2]:2 * b1[2], 2 * b0[1]:2 * b1[1], 2 * b0[0]:2 * b1[0]]
+        new = maxpool_box(sub)
+        old = blocks[b0[2]:b1[2], b0[1]:b1[1], b0[0]:b1[0]]
+        count += int(new.sum()) - int(old.sum())
+        blocks[b0[2]:b1[2], b0[1]:b1[1], b0[0]:b1[0]] = new
         n += 1
         if n % 8 == 0 or target < 4096:
-            if maxpool(occ, 2).sum() >= target:
+            if count >= target:
                 break
     return occ, n
+
+
+def maxpool_box(a: np.ndarray) -> np.ndarray:
+    """Max-pool by 2 along every axis of a box with even extents."""
+    z, y, x = a.shape
+    return a.reshape(z // 2, 2, y // 2, 2, x // 2, 2).max(axis=(1, 3, 5))
 
 
 # ----------------------------------------------------------------------------

@@ -12,10 +12,11 @@ import synth
 from paper_2302_12249_amd import merf
 
 HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "merf.h")
+SERVE_HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "merf_serve.h")
 
 
-def declared_functions():
-    src = open(HEADER).read()
+def declared_functions(path=HEADER):
+    src = open(path).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(merf_[a-z_]+)\s*\(", src)))
 
@@ -26,16 +27,43 @@ def test_header_declares_the_binding_exports():
 
 def test_library_exports_every_declared_symbol():
     lib = merf.load()
-    for name in declared_functions():
+    for name in declared_functions() + declared_functions(SERVE_HEADER):
         assert hasattr(lib, name), name
+
+
+def test_serve_header_declares_the_binding_exports():
+    assert declared_functions(SERVE_HEADER) == sorted(merf.SERVE_EXPORTS)
+
+
+@pytest.mark.parametrize("field,value", [("slots", 0), ("slots", 9), ("max_batch", 0), ("max_batch", 17),
+                                         ("struct_size", 8)])
+def test_server_config_rejected_before_device_calls(field, value):
+    lib = merf._serve_lib()
+    cfg = merf.server_config()
+    setattr(cfg, field, value)
+    h = C.c_void_p()
+    assert lib.merf_server_create(C.byref(cfg), C.byref(h)) == merf.MERF_E_INVALID
+    assert h.value is None
+    assert merf.last_error()
+
+
+def test_server_calls_reject_unknown_handles():
+    lib = merf._serve_lib()
+    bogus = C.c_void_p(0x1234)
+    assert lib.merf_server_destroy(bogus) == merf.MERF_E_INVALID
+    assert lib.merf_server_drain(bogus) == merf.MERF_E_INVALID
+    assert lib.merf_server_poll(bogus, 1) == merf.MERF_E_INVALID
+    st = merf.merf_server_stats()
+    assert lib.merf_server_get_stats(bogus, C.byref(st)) == merf.MERF_E_INVALID
 
 
 def test_struct_layouts_match_header(tmp_path):
     """sizeof/offsetof from the C compiler agree with the ctypes mirrors."""
     import subprocess
     structs = [("merf_scene_desc", merf.merf_scene_desc), ("merf_camera", merf.merf_camera),
-               ("merf_render_params", merf.merf_render_params)]
-    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "merf.h"', "int main(void) {"]
+               ("merf_render_params", merf.merf_render_params), ("merf_server_config", merf.merf_server_config),
+               ("merf_server_stats", merf.merf_server_stats)]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "merf_serve.h"', "int main(void) {"]
     for cname, cls in structs:
         lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
         for f, _ in cls._fields_:

@@ -1,0 +1,172 @@
+"""GPU tests of the serving runtime (include/merf_serve.h): continuous
+batching of uneven requests over several resident scenes must give every
+request exactly the image merf_render gives it alone; admission follows the
+device-memory budget."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from scene_builders import dense_scene
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+@pytest.fixture(scope="module")
+def merf():
+    from paper_2302_12249_amd import merf as m
+    m.load()
+    return m
+
+
+@pytest.fixture(scope="module")
+def scenes():
+    return [synth.preset_scene("tiny", seed=s) for s in (1, 2, 3)]
+
+
+def request_mix(n, seed):
+    rng = np.random.default_rng(seed)
+    sizes = [(64, 64), (96, 40), (13, 7), (128, 128), (33, 65)]
+    cams = synth.random_cameras(n, seed=seed, sizes=[sizes[i] for i in rng.integers(0, len(sizes), n)],
+                                inside=2.5)
+    scene_of = rng.integers(0, 3, n)
+    prec = [("f32", "f16", "bf16")[i] for i in rng.integers(0, 3, n)]
+    return cams, scene_of, prec
+
+
+def render_alone(torch, merf, scene, cams, i, prec):
+    r = merf.Renderer(scene)
+    try:
+        out = r.render(cams.subset(i), mlp_prec=prec)
+        torch.cuda.synchronize()
+        return out.cpu().numpy()
+    finally:
+        r.close()
+
+
+@pytest.mark.parametrize("use_graphs", [True, False])
+def test_mix_equals_alone(torch, merf, scenes, use_graphs):
+    say(f"serving: 24 uneven requests over 3 scenes, graphs={use_graphs}")
+    cams, scene_of, prec = request_mix(24, seed=7)
+    arr = merf.camera_array(cams)
+    srv = merf.Server(slots=3, max_batch=8, use_graphs=use_graphs)
+    try:
+        ids = [srv.add_scene(s) for s in scenes]
+        outs, tickets = [], []
+        for i in range(len(cams)):
+            w, h = cams.size[i]
+            outs.append(torch.full((int(w) * int(h), 4), float("nan"), device="cuda"))
+            p = merf.render_params(mlp_prec=prec[i])
+            tickets.append(srv.submit(ids[scene_of[i]], arr, i, outs[i].data_ptr(), p))
+        lats = [srv.wait(t)[0] for t in tickets]
+        st = srv.stats()
+        say(f"  launches {st['launches']} (graph {st['graph_launches']}), max in flight {st['max_inflight']}, "
+            f"latency p50 {np.percentile(lats, 50):.3f} ms")
+        assert st["completed"] == len(cams)
+        assert st["launches"] < len(cams)            # requests were fused
+        if use_graphs:
+            assert st["graph_launches"] == st["launches"]
+        for i in range(len(cams)):
+            alone = render_alone(torch, merf, scenes[scene_of[i]], cams, i, prec[i])
+            assert np.array_equal(outs[i].cpu().numpy(), alone), i
+    finally:
+        srv.close()
+
+
+def test_arrivals_while_running_are_admitted(torch, merf, scenes):
+    say("serving: requests arriving from another thread while launches run")
+    cams, scene_of, prec = request_mix(40, seed=11)
+    arr = merf.camera_array(cams)
+    srv = merf.Server(slots=4, max_batch=4, use_graphs=True)
+    try:
+        ids = [srv.add_scene(s) for s in scenes]
+        outs = [torch.empty((int(w) * int(h), 4), device="cuda") for w, h in cams.size]
+        tickets = [None] * len(cams)
+
+        def producer():
+            for i in range(len(cams)):
+                tickets[i] = srv.submit(ids[scene_of[i]], arr, i, outs[i].data_ptr(), merf.render_params())
+                time.sleep(0.0002)
+
+        th = threading.Thread(target=producer)
+        th.start()
+        th.join()
+        srv.drain()
+        st = srv.stats()
+        say(f"  launches {st['launches']}, max in flight {st['max_inflight']}")
+        assert st["completed"] == len(cams)
+        for i in (0, 17, 39):
+            alone = render_alone(torch, merf, scenes[scene_of[i]], cams, i, "f32")
+            assert np.array_equal(outs[i].cpu().numpy(), alone)
+        for t in tickets:
+            lat, q = srv.wait(t)
+            assert lat >= q >= 0.0
+    finally:
+        srv.close()
+
+
+def test_admission_by_budget_and_eviction(torch, merf, scenes):
+    say("serving: scene admission under an HBM budget")
+    probe = merf.Server(slots=1)
+    sid = probe.add_scene(scenes[0])
+    one = probe.stats()["resident_bytes"]
+    probe.close()
+    budget = 2 * one + one // 2                        # room for two scenes
+    srv = merf.Server(slots=2, hbm_budget=budget)
+    try:
+        a, b = srv.add_scene(scenes[0]), srv.add_scene(scenes[1])
+        with pytest.raises(merf.MerfError) as e:
+            srv.add_scene(scenes[2])
+        assert e.value.code == merf.MERF_E_OOM
+        assert srv.stats()["resident_scenes"] == 2
+        srv.remove_scene(a)
+        c = srv.add_scene(scenes[2])
+        assert srv.stats()["resident_bytes"] <= budget
+    finally:
+        srv.close()
+    srv = merf.Server(slots=2, hbm_budget=budget, evict_idle=True)
+    try:
+        ids = [srv.add_scene(s) for s in scenes]         # the third evicts the least recently used
+        st = srv.stats()
+        assert st["evictions"] == 1 and st["resident_scenes"] == 2
+        cams = synth.tiny_camera(w=32, h=32)
+        out = torch.empty((32 * 32, 4), device="cuda")
+        with pytest.raises(merf.MerfError):
+            srv.submit(ids[0], merf.camera_array(cams), 0, out.data_ptr(), merf.render_params())
+        t = srv.submit(ids[2], merf.camera_array(cams), 0, out.data_ptr(), merf.render_params())
+        srv.wait(t)
+    finally:
+        srv.close()
+
+
+def test_busy_scene_cannot_be_removed(torch, merf, scenes):
+    say("serving: removing a scene with queued work is refused")
+    srv = merf.Server(slots=1, max_batch=1)
+    try:
+        sid = srv.add_scene(scenes[0])
+        cams = synth.tiny_camera(w=128, h=128)
+        arr = merf.camera_array(cams)
+        outs = [torch.empty((128 * 128, 4), device="cuda") for _ in range(8)]
+        ts = [srv.submit(sid, arr, 0, o.data_ptr(), merf.render_params()) for o in outs]
+        busy = not srv.poll(ts[-1])
+        if busy:
+            with pytest.raises(merf.MerfError):
+                srv.remove_scene(sid)
+        srv.drain()
+        srv.remove_scene(sid)
+        assert srv.stats()["resident_scenes"] == 0
+    finally:
+        srv.close()

@@ -53,3 +53,13 @@ def test_tables_are_monotone_and_distinct_where_expected(fmt):
         assert t[0] == -m and t[255] == m
         bits = to_bits(t, fmt)
         assert bits.shape == (256,)
+
+
+@pytest.mark.parametrize("m", [7, 14])
+def test_fp16_dequant_by_fp32_fma_is_exact(m):
+    """The renderer's FP16 feature path computes RN16(RN32(b * RN32(2m/255) - m));
+    for every code this equals the correctly rounded float16 of 2mb/255 - m."""
+    a32 = Fraction(round_fraction(Fraction(2 * m, 255), "f32"))
+    for b in range(256):
+        fma32 = round_fraction(Fraction(b) * a32 - m, "f32")
+        assert round_fraction(Fraction(fma32), "f16") == round_fraction(dequant_exact(b, m), "f16"), b
