@@ -138,6 +138,164 @@ def serving_leg(n_requests: int, seed: int = 200):
             "graph_launches": int(st["graph_launches"]), "max_inflight": int(st["max_inflight"])}
 
 
+def precision_workload(steps: int):
+    """Precision config: the full-size scene as 16 seeded 1920x1080 orbit views in
+    one batched render call; fp32 / fp16 / bf16 MLP and fp16 features, each
+    against the FP64 oracle on every 64th row of every view."""
+    import numpy as np
+    import torch
+    import oracle
+    import synth
+    from paper_2302_12249_amd import merf
+
+    scene = synth.preset_scene("full")
+    cams = synth.orbit_cameras(16)
+    rays = cams.num_pixels()
+    r = merf.Renderer(scene)
+    stream = torch.cuda.current_stream()
+    out = torch.empty((rays, 4), dtype=torch.float32, device="cuda")
+    W, H = 1920, 1080
+    ref, st = oracle.render(scene, cams, rows_stride=64, row_offset=31, fragile=True)
+    rows = np.arange(31, H, 64)
+    sel = np.concatenate([(c * W * H + rows[:, None] * W + np.arange(W)[None, :]).reshape(-1) for c in range(16)])
+    ok = st["fragile"] == 0
+    res = {}
+    for name, mlp, feat in (("f32", "f32", "f32"), ("mlp_f16", "f16", "f32"), ("mlp_bf16", "bf16", "f32"),
+                            ("feat_f16_mlp_f16", "f16", "f16"), ("feat_f16_mlp_bf16", "bf16", "f16")):
+        for _ in range(2):
+            r.render(cams, out=out, mlp_prec=mlp, feat_prec=feat)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            r.render(cams, out=out, mlp_prec=mlp, feat_prec=feat)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        d = out.cpu().numpy()[sel].astype(np.float64) - ref
+        res[name] = {"ms_per_step": ms, "Mrays/s": rays / (ms * 1e-3) / 1e6,
+                     "psnr_db": 10 * np.log10(1 / max(float(np.mean(d[:, :3] ** 2)), 1e-30)),
+                     "psnr_db_nonfragile": 10 * np.log10(1 / max(float(np.mean(d[ok, :3] ** 2)), 1e-30)),
+                     "max_abs_nonfragile": float(np.abs(d[ok]).max()), "mean_abs": float(np.abs(d).mean())}
+    r.close()
+    return {"metric": "Mrays/s, 16 x 1080p views (precision config)", "value": res["f32"]["Mrays/s"],
+            "unit": "Mrays/s", "n_gpus": 1, "steps": steps, "higher_is_better": True, "data": "synthetic",
+            "config": {"workload": "full-size scene, 16 orbit views at 1920x1080 in one call", "rays_per_step": rays,
+                       "oracle_rows": "every 64th row of every view"},
+            "precision": res}
+
+
+def stress_workload(n_scenes: int, n_requests: int):
+    """Stress config: n_scenes resident 512^3/2048^2 scenes at up to 25% block
+    occupancy, half step (2/R), 3840x2160 requests mixed with 512^2 requests,
+    bf16 MLP through the server; beside the plain fp32 renderer (one request
+    per merf_render call) on the same requests."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2302_12249_amd import merf
+
+    rng = np.random.default_rng(300)
+    srv = merf.Server(slots=4, max_batch=16, use_graphs=True)
+    ids, gen_s = [], 0.0
+    scenes = []
+    try:
+        for k in range(n_scenes):
+            t0 = time.perf_counter()
+            sc = synth.make_scene(512, 2048, float(rng.uniform(0.05, 0.25)), 1.99, 0.05, 0.25, pools=(8, 2, 1),
+                                  seed=300 + k, mlp_seed=5300 + k, name=f"stress{k}")
+            gen_s += time.perf_counter() - t0
+            ids.append(srv.add_scene(sc))
+            scenes.append(sc if k < 2 else None)          # keep two for the plain comparison
+            del sc
+        sizes = [(3840, 2160) if rng.random() < 0.25 else (512, 512) for _ in range(n_requests)]
+        cams = synth.random_cameras(n_requests, seed=301, sizes=sizes)
+        scene_of = rng.integers(0, n_scenes, n_requests)
+        arr = merf.camera_array(cams)
+        step = 2.0 / 2048
+        p16 = merf.render_params(step=step, mlp_prec="bf16")
+        outs = [torch.empty((w * h, 4), dtype=torch.float32, device="cuda") for (w, h) in sizes]
+        rays = sum(w * h for (w, h) in sizes)
+        for _ in range(2):
+            tk = [srv.submit(ids[scene_of[i]], arr, i, outs[i].data_ptr(), p16) for i in range(n_requests)]
+            lat = np.array([srv.wait(t)[0] for t in tk])
+        t0 = time.perf_counter()
+        tk = [srv.submit(ids[scene_of[i]], arr, i, outs[i].data_ptr(), p16) for i in range(n_requests)]
+        lat = np.array([srv.wait(t)[0] for t in tk])
+        span = time.perf_counter() - t0
+        st = srv.stats()
+        # plain fp32 renderer on the requests of the two kept scenes
+        plain = []
+        for k in (0, 1):
+            rr = merf.Renderer(scenes[k])
+            idx = [i for i in range(n_requests) if scene_of[i] == k][:8]
+            for i in idx:
+                for _ in range(2):
+                    rr.render(cams.subset(i), out=outs[i], step=step)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                rr.render(cams.subset(i), out=outs[i], step=step)
+                torch.cuda.synchronize()
+                plain.append((sizes[i][0] * sizes[i][1], time.perf_counter() - t1))
+            rr.close()
+    finally:
+        srv.close()
+    prays = sum(n for n, _ in plain)
+    ptime = sum(t for _, t in plain)
+    return {"metric": "served Mrays/s and p50/p99 latency (stress config)", "value": rays / span / 1e6,
+            "unit": "Mrays/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+            "config": {"workload": f"{n_scenes} resident 512^3/2048^2 scenes (5-25% occupancy), step 2/R, "
+                                   f"{n_requests} requests 3840x2160 or 512^2, bf16 MLP",
+                       "resident_bytes": int(st["resident_bytes"]), "scene_generation_s": gen_s},
+            "served": {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                       "launches": int(st["launches"]), "max_inflight": int(st["max_inflight"])},
+            "plain_fp32_Mrays/s": prays / ptime / 1e6 if ptime > 0 else None}
+
+
+def variants_workload(steps: int):
+    """Representation variants on the full-size camera: MERF (512^3 grid +
+    2048^2 planes), the same scene without its grid (planes only, the paper's
+    Sec. 7 ablation) and block-sparse grids without planes (512^3 and 1024^3,
+    in the spirit of the SNeRG++ comparison): device bytes against Mrays/s."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2302_12249_amd import merf
+
+    full = synth.preset_scene("full")
+    cams = synth.full_camera()
+    rays = cams.num_pixels()
+    variants = [("merf_L512_R2048", full), ("planes_only_R2048", synth.planes_only(full)),
+                ("grid_only_L512", synth.grid_only_scene(512, 0.05, seed=2)),
+                ("grid_only_L1024", synth.grid_only_scene(1024, 0.05, seed=2))]
+    out = torch.empty((rays, 4), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, sc in variants:
+        r = merf.Renderer(sc)
+        st = torch.zeros(8, dtype=torch.int64, device="cuda")
+        r.render(cams, out=out, stats=st)
+        for _ in range(3):
+            r.render(cams, out=out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            r.render(cams, out=out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        cnt = st.cpu().numpy()
+        res[name] = {"device_bytes": merf.scene_bytes(r.handle), "ms_per_frame": ms,
+                     "Mrays/s": rays / (ms * 1e-3) / 1e6, "evaluated_per_ray": float(cnt[3]) / rays,
+                     "step": sc.step}
+        r.close()
+    return {"metric": "Mrays/s at 1080p and device bytes per representation", "value": res["merf_L512_R2048"]["Mrays/s"],
+            "unit": "Mrays/s", "n_gpus": 1, "steps": steps, "higher_is_better": True, "data": "synthetic",
+            "config": {"workload": "full-size camera, four representations of the same kind of scene"},
+            "variants": res}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +303,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["full", "precision", "stress", "variants"], default="full",
+                    help="full (default, the headline line), precision (16 x 1080p views), stress, "
+                         "or variants (representations: memory against speed)")
+    ap.add_argument("--stress-scenes", type=int, default=32)
     ap.add_argument("--serve-requests", type=int, default=240,
                     help="requests in the serving-mix leg (0 skips it)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -163,6 +325,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "precision":
+        print(json.dumps(precision_workload(args.steps)), flush=True)
+        return
+    if args.workload == "variants":
+        print(json.dumps(variants_workload(args.steps)), flush=True)
+        return
+    if args.workload == "stress":
+        print(json.dumps(stress_workload(args.stress_scenes, args.serve_requests)), flush=True)
+        return
     scene = synth.preset_scene("full")
     cams = synth.full_camera()
     rays = cams.num_pixels()

@@ -107,7 +107,8 @@ typedef struct {
     int32_t delta_mode;                   /* 0: delta = contracted interval length;
                                              1: world length of its preimage */
     int32_t mlp_prec;                     /* deferred MLP: 0 = fp32, 1 = fp16, 2 = bf16 */
-    int32_t feat_prec;                    /* feature interpolation: 0 = fp32, 1 = fp16 */
+    int32_t feat_prec;                    /* 0 = codes interpolated in fp32; 1 = every code
+                                             dequantised to float16 first (sums stay fp32) */
     uint64_t *stats_dev;                  /* NULL, or device uint64[8] to which the render
                                              ADDS: [0] rays, [1] occupancy lookups,
                                              [2] lattice samples visited, [3] samples
@@ -170,6 +171,20 @@ size_t merf_scene_bytes(merf_scene_t s);
  */
 int merf_dequantize(const uint8_t *codes_dev, int64_t n, float m, int32_t prec, void *out_dev,
                     void *hip_stream);
+
+/*
+ * Occupancy hierarchy by max-pooling (Sec. 6: the renderer's occupancy grids
+ * are max-pools of the full-resolution binary mask A of Sec. 5.3).
+ * mask_dev: device uint8 [res^3] z-major, nonzero = occupied.  For each level
+ * l, out_dev[l] (device, (res / factors[l])^3 bytes, caller-owned) receives 1
+ * where any cell of the factors[l]^3 block is occupied, else 0.  factors[l]
+ * must divide res; factor 1 copies the mask as 0/1.  Host arrays factors and
+ * out_dev are read during the call.  Asynchronous on hip_stream.
+ * Errors: MERF_E_INVALID for res outside [1, 2048], n_levels outside [1, 8],
+ * a factor that does not divide res, or NULL buffers.
+ */
+int merf_occupancy_pyramid(const uint8_t *mask_dev, int32_t res, const int32_t *factors, int32_t n_levels,
+                           uint8_t *const *out_dev, void *hip_stream);
 
 #ifdef __cplusplus
 }

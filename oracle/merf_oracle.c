@@ -253,28 +253,33 @@ static int plane_byte(const or_scene *s, int plane, int u, int v, int c)
 }
 
 /* Eq. 5: t(p) = V(p) + P_x(p_y, p_z) + P_y(p_x, p_z) + P_z(p_x, p_y), with
- * each stored byte dequantised (Eq. 8) before interpolation. */
+ * each stored byte dequantised (Eq. 8) before interpolation.  A scene without
+ * the 3D grid (L = 0, the representation the paper ablates in Sec. 7) sums the
+ * planes only; a scene without planes (R = 0) is the sparse grid alone. */
 void or_features(const or_scene *s, const double p[3], double t[8])
 {
-    int gi[3][2];
-    double gf[3];
-    for (int a = 0; a < 3; ++a) texel_coord(p[a], s->L, &gi[a][0], &gi[a][1], &gf[a]);
-    int pi[3][2];
-    double pf[3];
-    for (int a = 0; a < 3; ++a) texel_coord(p[a], s->R, &pi[a][0], &pi[a][1], &pf[a]);
+    const int has_grid = s->L > 0, has_planes = s->R > 0;
+    int gi[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    double gf[3] = {0, 0, 0};
+    if (has_grid)
+        for (int a = 0; a < 3; ++a) texel_coord(p[a], s->L, &gi[a][0], &gi[a][1], &gf[a]);
+    int pi[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    double pf[3] = {0, 0, 0};
+    if (has_planes)
+        for (int a = 0; a < 3; ++a) texel_coord(p[a], s->R, &pi[a][0], &pi[a][1], &pf[a]);
     /* (u axis, v axis) of planes P_x, P_y, P_z */
     static const int uax[3] = {1, 0, 0}, vax[3] = {2, 2, 1};
     for (int c = 0; c < s->C; ++c) {
         double m = channel_m(s, c);
         double v = 0.0;
-        for (int dz = 0; dz < 2; ++dz)
+        for (int dz = 0; dz < 2 && has_grid; ++dz)
             for (int dy = 0; dy < 2; ++dy)
                 for (int dx = 0; dx < 2; ++dx) {
                     double w = (dx ? gf[0] : 1.0 - gf[0]) * (dy ? gf[1] : 1.0 - gf[1]) *
                                (dz ? gf[2] : 1.0 - gf[2]);
                     v += w * or_dequant(grid_byte(s, gi[0][dx], gi[1][dy], gi[2][dz], c), m);
                 }
-        for (int pl = 0; pl < 3; ++pl) {
+        for (int pl = 0; pl < 3 && has_planes; ++pl) {
             int ua = uax[pl], va = vax[pl];
             for (int dv = 0; dv < 2; ++dv)
                 for (int du = 0; du < 2; ++du) {

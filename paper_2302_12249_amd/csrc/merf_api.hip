@@ -72,17 +72,19 @@ int validate_desc(const merf_scene_desc *d) {
                     sizeof(merf_scene_desc));
     if (d->block_size != kBlock) return fail(MERF_E_INVALID, "block_size must be %d (got %d)", kBlock, d->block_size);
     if (d->channels != kChannels) return fail(MERF_E_INVALID, "channels must be %d (got %d)", kChannels, d->channels);
-    if (d->grid_res < 2 * kBlock || d->grid_res % kBlock != 0 || d->grid_res > 4096)
-        return fail(MERF_E_INVALID, "grid_res %d must be a multiple of 8 in [16, 4096]", d->grid_res);
+    // grid_res = 0: planes only (no 3D grid); plane_res = 0: sparse grid only
+    if (d->grid_res != 0 && (d->grid_res < 2 * kBlock || d->grid_res % kBlock != 0 || d->grid_res > 4096))
+        return fail(MERF_E_INVALID, "grid_res %d must be 0 or a multiple of 8 in [16, 4096]", d->grid_res);
+    if (d->grid_res == 0 && d->plane_res == 0) return fail(MERF_E_INVALID, "scene has neither grid nor planes");
     // the kernels address every array with 32-bit byte offsets
-    if (d->plane_res < 2 || d->plane_res > 8192)
-        return fail(MERF_E_INVALID, "plane_res %d must be in [2, 8192]", d->plane_res);
+    if (d->plane_res != 0 && (d->plane_res < 2 || d->plane_res > 8192))
+        return fail(MERF_E_INVALID, "plane_res %d must be 0 or in [2, 8192]", d->plane_res);
     const int64_t nbl = d->grid_res / kBlock;
     if (d->num_blocks < 0 || d->num_blocks > nbl * nbl * nbl)
         return fail(MERF_E_INVALID, "num_blocks %d out of range", d->num_blocks);
-    if (!d->block_index) return fail(MERF_E_INVALID, "block_index is NULL");
+    if (nbl > 0 && !d->block_index) return fail(MERF_E_INVALID, "block_index is NULL");
     if (d->num_blocks > 0 && !d->blocks) return fail(MERF_E_INVALID, "blocks is NULL");
-    if (!d->planes) return fail(MERF_E_INVALID, "planes is NULL");
+    if (d->plane_res > 0 && !d->planes) return fail(MERF_E_INVALID, "planes is NULL");
     if (d->occ_levels < 1 || d->occ_levels > MERF_MAX_OCC_LEVELS)
         return fail(MERF_E_INVALID, "occ_levels %d must be in [1, %d]", d->occ_levels, MERF_MAX_OCC_LEVELS);
     for (int l = 0; l < d->occ_levels; ++l) {
@@ -156,47 +158,29 @@ Layout make_layout(const merf_scene_desc *d, int64_t nbricks) {
 // Bricks with a one-voxel apron: brick (bx, by, bz) holds voxels 8b .. 8b+8 of
 // each axis.  A brick is stored when any of the 8 blocks it touches is stored;
 // all other index entries point at one shared all-zero brick (the last).
-void build_bricks(const merf_scene_desc *d, std::vector<int32_t> &bidx, std::vector<uint8_t> &bricks) {
-    const int L = d->grid_res, nbl = L / kBlock;
-    auto block_at = [&](int bx, int by, int bz) -> int32_t {
-        if (bx >= nbl || by >= nbl || bz >= nbl) return -1;
-        return d->block_index[((size_t)bz * nbl + by) * nbl + bx];
+// The host only assigns the slots; the device packs the voxels.
+void assign_bricks(const merf_scene_desc *d, std::vector<int32_t> &bidx, std::vector<int32_t> &pos) {
+    const int nbl = d->grid_res / kBlock;
+    auto stored = [&](int bx, int by, int bz) {
+        return bx < nbl && by < nbl && bz < nbl && d->block_index[((size_t)bz * nbl + by) * nbl + bx] >= 0;
     };
     bidx.assign((size_t)nbl * nbl * nbl, -1);
-    int32_t n = 0;
+    pos.clear();
     for (int bz = 0; bz < nbl; ++bz)
         for (int by = 0; by < nbl; ++by)
             for (int bx = 0; bx < nbl; ++bx) {
                 bool need = false;
                 for (int dz = 0; dz < 2 && !need; ++dz)
                     for (int dy = 0; dy < 2 && !need; ++dy)
-                        for (int dx = 0; dx < 2 && !need; ++dx) need = block_at(bx + dx, by + dy, bz + dz) >= 0;
-                if (need) bidx[((size_t)bz * nbl + by) * nbl + bx] = n++;
+                        for (int dx = 0; dx < 2 && !need; ++dx) need = stored(bx + dx, by + dy, bz + dz);
+                if (need) {
+                    bidx[((size_t)bz * nbl + by) * nbl + bx] = (int32_t)pos.size();
+                    pos.push_back(bx | (by << 10) | (bz << 20));
+                }
             }
-    // one extra all-zero brick stands for every absent brick, so the kernel
-    // never branches on the index
-    const int32_t zero = n;
+    const int32_t zero = (int32_t)pos.size();
     for (int32_t &b : bidx)
         if (b < 0) b = zero;
-    bricks.assign((size_t)(n + 1) * kBrickBytes, 0);
-    for (int bz = 0; bz < nbl; ++bz)
-        for (int by = 0; by < nbl; ++by)
-            for (int bx = 0; bx < nbl; ++bx) {
-                int32_t slot = bidx[((size_t)bz * nbl + by) * nbl + bx];
-                if (slot == zero) continue;
-                uint8_t *dst = bricks.data() + (size_t)slot * kBrickBytes;
-                for (int lz = 0; lz < kBrick; ++lz)
-                    for (int ly = 0; ly < kBrick; ++ly)
-                        for (int lx = 0; lx < kBrick; ++lx) {
-                            int x = bx * kBlock + lx, y = by * kBlock + ly, z = bz * kBlock + lz;
-                            if (x >= L || y >= L || z >= L) continue;
-                            int32_t src = block_at(x / kBlock, y / kBlock, z / kBlock);
-                            if (src < 0) continue;
-                            const uint8_t *s = d->blocks + ((((size_t)src * kBlock + (z % kBlock)) * kBlock +
-                                                             (y % kBlock)) * kBlock + (x % kBlock)) * kChannels;
-                            std::memcpy(dst + (((size_t)lz * kBrick + ly) * kBrick + lx) * kChannels, s, kChannels);
-                        }
-            }
 }
 
 }  // namespace
@@ -210,11 +194,11 @@ size_t scene_device_bytes(const merf_scene_desc *desc) {
     return make_layout(desc, count_bricks(desc)).total;
 }
 
-int check_params(const merf_render_params *p, int R, float *step_out) {
+int check_params(const merf_render_params *p, int res, float *step_out) {
     if (!p) return fail(MERF_E_INVALID, "render params are NULL");
     if (p->struct_size != sizeof(merf_render_params))
         return fail(MERF_E_INVALID, "params struct_size %u != %zu", p->struct_size, sizeof(merf_render_params));
-    const float step = p->step > 0.0f ? p->step : 4.0f / (float)R;
+    const float step = p->step > 0.0f ? p->step : 4.0f / (float)res;
     if (!std::isfinite(step) || step < 1e-6f) return fail(MERF_E_INVALID, "step %g out of range", (double)p->step);
     if (!(p->t_min >= 0.0f && p->t_min < 1.0f)) return fail(MERF_E_INVALID, "t_min %g not in [0, 1)", (double)p->t_min);
     if (p->delta_mode != 0 && p->delta_mode != 1) return fail(MERF_E_INVALID, "delta_mode %d", p->delta_mode);
@@ -292,9 +276,8 @@ int merf_scene_upload(const merf_scene_desc *desc, merf_scene_t *out) {
     const int64_t nbricks = count_bricks(desc);
     if ((nbricks + 1) * (int64_t)kBrickBytes >= (int64_t)1 << 31)
         return fail(MERF_E_INVALID, "%lld bricks exceed the 2 GiB addressed by 32-bit offsets", (long long)nbricks);
-    std::vector<int32_t> bidx;
-    std::vector<uint8_t> bricks;
-    build_bricks(desc, bidx, bricks);
+    std::vector<int32_t> bidx, bpos;
+    assign_bricks(desc, bidx, bpos);
     const int L = desc->grid_res, R = desc->plane_res, nbl = L / kBlock;
     const Layout lay = make_layout(desc, nbricks);
     const size_t o_bidx = lay.bidx, o_bricks = lay.bricks, o_planes = lay.planes, o_mlp = lay.mlp, total = lay.total;
@@ -311,40 +294,57 @@ int merf_scene_upload(const merf_scene_desc *desc, merf_scene_t *out) {
         g_in_use -= total;
     };
 
-    void *base = nullptr;
+    // resident allocation + staging for the raw blocks, their index and the
+    // brick positions (freed once the bricks are packed)
+    const size_t raw_blocks = (size_t)desc->num_blocks * kBlock * kBlock * kBlock * kChannels;
+    const size_t s_blocks = 0, s_index = align_up(std::max<size_t>(raw_blocks, 8), 256),
+                 s_pos = s_index + align_up((size_t)nbl * nbl * nbl * sizeof(int32_t), 256),
+                 staging = s_pos + align_up(std::max<size_t>(bpos.size(), 1) * sizeof(int32_t), 256);
+    void *base = nullptr, *stage = nullptr;
     hipError_t e = hipMalloc(&base, total);
-    if (e != hipSuccess || !base) {
+    if (e == hipSuccess) e = hipMalloc(&stage, staging);
+    if (e != hipSuccess || !base || !stage) {
         (void)hipGetLastError();
+        if (base) (void)hipFree(base);
         release();
-        return fail(MERF_E_OOM, "hipMalloc(%zu) failed: %s", total, hipGetErrorString(e));
+        return fail(MERF_E_OOM, "hipMalloc (%zu + %zu staging bytes) failed: %s", total, staging, hipGetErrorString(e));
     }
     auto dev = [&](size_t o) { return static_cast<uint8_t *>(base) + o; };
-    struct Copy { size_t off; const void *src; size_t n; };
+    auto stg = [&](size_t o) { return static_cast<uint8_t *>(stage) + o; };
+    struct Copy { uint8_t *dst; const void *src; size_t n; };
     std::vector<Copy> copies = {
-        {o_bidx, bidx.data(), bidx.size() * sizeof(int32_t)},
-        {o_bricks, bricks.data(), bricks.size()},
-        {o_planes, desc->planes, (size_t)3 * R * R * kChannels},
-        {o_mlp, desc->mlp_params, kMlpParams * sizeof(float)},
+        {dev(o_bidx), bidx.data(), bidx.size() * sizeof(int32_t)},
+        {dev(o_planes), desc->planes, (size_t)3 * R * R * kChannels},
+        {dev(o_mlp), desc->mlp_params, kMlpParams * sizeof(float)},
+        {stg(s_blocks), desc->blocks, raw_blocks},
+        {stg(s_index), desc->block_index, (size_t)nbl * nbl * nbl * sizeof(int32_t)},
+        {stg(s_pos), bpos.data(), bpos.size() * sizeof(int32_t)},
     };
     for (int l = 0; l < desc->occ_levels; ++l) {
         size_t r = (size_t)desc->occ_res[l];
-        copies.push_back({o_occ[l], desc->occ[l], r * r * r});
+        copies.push_back({dev(o_occ[l]), desc->occ[l], r * r * r});
     }
     for (const Copy &c : copies) {
         if (c.n == 0) continue;
-        e = hipMemcpy(dev(c.off), c.src, c.n, hipMemcpyHostToDevice);
-        if (e != hipSuccess) {
-            (void)hipFree(base);
-            release();
-            return hip_fail(e, "hipMemcpy (scene upload)");
-        }
+        e = hipMemcpy(c.dst, c.src, c.n, hipMemcpyHostToDevice);
+        if (e != hipSuccess) break;
+    }
+    if (e == hipSuccess)
+        e = launch_pack_bricks(stg(s_blocks), reinterpret_cast<const int32_t *>(stg(s_index)),
+                               reinterpret_cast<const int32_t *>(stg(s_pos)), (int)nbricks, L, dev(o_bricks), nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    (void)hipFree(stage);
+    if (e != hipSuccess) {
+        (void)hipFree(base);
+        release();
+        return hip_fail(e, "scene upload");
     }
 
     merf_scene *s = new merf_scene();
     s->magic = kMagic;
     s->dev_base = base;
     s->dev_bytes = total;
-    s->nbricks = (int32_t)(bricks.size() / kBrickBytes);
+    s->nbricks = (int32_t)nbricks;
     DevScene &ds = s->ds;
     ds.brick_index = reinterpret_cast<const int32_t *>(dev(o_bidx));
     ds.bricks = dev(o_bricks);
@@ -394,7 +394,7 @@ int merf_render(merf_scene_t s, const merf_camera *cams, int32_t n_cams, const m
     clear_error();
     if (!live(s)) return fail(MERF_E_INVALID, "merf_render: invalid scene handle");
     float step = 0.0f;
-    int rc = check_params(p, s->ds.R, &step);
+    int rc = check_params(p, std::max(s->ds.R, s->ds.L), &step);
     if (rc) return rc;
     if (n_cams < 0) return fail(MERF_E_INVALID, "n_cams %d < 0", n_cams);
     if (n_cams == 0) return MERF_OK;
@@ -427,6 +427,25 @@ int merf_dequantize(const uint8_t *codes_dev, int64_t n, float m, int32_t prec, 
     if (prec < 0 || prec > 2) return fail(MERF_E_INVALID, "prec %d not in {0, 1, 2}", prec);
     hipError_t e = launch_dequant(codes_dev, n, m, prec, out_dev, static_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return hip_fail(e, "dequant launch");
+    return MERF_OK;
+}
+
+int merf_occupancy_pyramid(const uint8_t *mask_dev, int32_t res, const int32_t *factors, int32_t n_levels,
+                           uint8_t *const *out_dev, void *hip_stream) {
+    clear_error();
+    if (res < 1 || res > 2048) return fail(MERF_E_INVALID, "res %d not in [1, 2048]", res);
+    if (n_levels < 1 || n_levels > 8) return fail(MERF_E_INVALID, "n_levels %d not in [1, 8]", n_levels);
+    if (!mask_dev || !factors || !out_dev) return fail(MERF_E_INVALID, "NULL buffer");
+    for (int l = 0; l < n_levels; ++l) {
+        if (factors[l] < 1 || res % factors[l] != 0)
+            return fail(MERF_E_INVALID, "factor %d does not divide res %d", factors[l], res);
+        if (!out_dev[l]) return fail(MERF_E_INVALID, "out_dev[%d] is NULL", l);
+    }
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    for (int l = 0; l < n_levels; ++l) {
+        hipError_t e = launch_maxpool(mask_dev, res, factors[l], out_dev[l], stream);
+        if (e != hipSuccess) return hip_fail(e, "max-pool launch");
+    }
     return MERF_OK;
 }
 

@@ -64,5 +64,9 @@ const void *render_kernel(const RenderBatch &rb);
 dim3 render_grid(const RenderBatch &rb);
 constexpr int kRenderBlock = 64;
 hipError_t launch_dequant(const uint8_t *codes, int64_t n, float m, int prec, void *out, hipStream_t stream);
+// merf_ingest.hip: brick_pos[i] = bx | by << 10 | bz << 20 of brick slot i.
+hipError_t launch_pack_bricks(const uint8_t *blocks, const int32_t *block_index, const int32_t *brick_pos,
+                              int nbricks, int L, uint8_t *bricks, hipStream_t stream);
+hipError_t launch_maxpool(const uint8_t *in, int rin, int f, uint8_t *out, hipStream_t stream);
 
 }  // namespace merf

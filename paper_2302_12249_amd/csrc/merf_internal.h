@@ -21,9 +21,10 @@ const DevScene *scene_dev(merf_scene_t s);
 // Device bytes merf_scene_upload would allocate for desc (0 if desc is invalid).
 size_t scene_device_bytes(const merf_scene_desc *desc);
 
-// Validate render parameters for a scene of plane resolution R; on success
-// stores the effective contracted step.
-int check_params(const merf_render_params *p, int R, float *step);
+// Validate render parameters; res is the finest scene resolution max(R, L),
+// whose texel size 4/res is the default step.  On success stores the
+// effective contracted step.
+int check_params(const merf_render_params *p, int res, float *step);
 int check_camera(const merf_camera &c, int index);
 
 // Start a launch descriptor (no cameras yet) / append one camera whose

@@ -195,57 +195,34 @@ __device__ __forceinline__ u32x4 load_pair(const uint8_t *base, uint32_t off) {
 // added to uniform base pointers, so no 64-bit address arithmetic runs per lane.
 template <bool kStats, bool kFeatF16>
 __device__ __forceinline__ void shade_sample(const DevScene &sc, float3 p, float delta, Accum &acc, Counters &cnt) {
-    // ---- three planes: bilinear.  Their addresses depend on no load, so they
-    // are issued first and overlap the brick-index round trip below.
-    const float ps = (float)sc.R * 0.25f, pmax = (float)(sc.R - 1);
-    float hx = fminf(fmaxf(fmaf(p.x + 2.0f, ps, -0.5f), 0.0f), pmax);
-    float hy = fminf(fmaxf(fmaf(p.y + 2.0f, ps, -0.5f), 0.0f), pmax);
-    float hz = fminf(fmaxf(fmaf(p.z + 2.0f, ps, -0.5f), 0.0f), pmax);
-    int jx = min((int)hx, sc.R - 2), jy = min((int)hy, sc.R - 2), jz = min((int)hz, sc.R - 2);
-    float ex = hx - (float)jx, ey = hy - (float)jy, ez = hz - (float)jz;
-    const uint32_t row = (uint32_t)sc.R * kChannels, plane = (uint32_t)sc.R * row;
-    const uint32_t o0 = (uint32_t)jz * row + (uint32_t)jy * kChannels;              // P_x(y, z)
-    const uint32_t o1 = plane + (uint32_t)jz * row + (uint32_t)jx * kChannels;      // P_y(x, z)
-    const uint32_t o2 = 2u * plane + (uint32_t)jy * row + (uint32_t)jx * kChannels; // P_z(x, y)
-    u32x4 t[6];   // each = texels (u, v) and (u + 1, v)
-    t[0] = load_pair(sc.planes, o0);
-    t[1] = load_pair(sc.planes, o0 + row);
-    t[2] = load_pair(sc.planes, o1);
-    t[3] = load_pair(sc.planes, o1 + row);
-    t[4] = load_pair(sc.planes, o2);
-    t[5] = load_pair(sc.planes, o2 + row);
-    // ---- sparse 3D grid: trilinear footprint inside one apron brick.  Every
-    // index entry is a valid brick (absent blocks point at an all-zero brick),
-    // so the corner loads need no branch.
-    const float gs = (float)sc.L * 0.25f, gmax = (float)(sc.L - 1);
-    float gx = fminf(fmaxf(fmaf(p.x + 2.0f, gs, -0.5f), 0.0f), gmax);
-    float gy = fminf(fmaxf(fmaf(p.y + 2.0f, gs, -0.5f), 0.0f), gmax);
-    float gz = fminf(fmaxf(fmaf(p.z + 2.0f, gs, -0.5f), 0.0f), gmax);
-    int ix = min((int)gx, sc.L - 2), iy = min((int)gy, sc.L - 2), iz = min((int)gz, sc.L - 2);
-    float fx = gx - (float)ix, fy = gy - (float)iy, fz = gz - (float)iz;
-    const uint32_t bi = ((uint32_t)(iz >> 3) * sc.nbl + (uint32_t)(iy >> 3)) * sc.nbl + (uint32_t)(ix >> 3);
-    const int brick = load_at<int>(reinterpret_cast<const uint8_t *>(sc.brick_index), bi * 4u);
-    const uint32_t ob = (uint32_t)brick * kBrickBytes +
-                        (uint32_t)((((iz & 7) * kBrick + (iy & 7)) * kBrick + (ix & 7)) * kChannels);
-    constexpr uint32_t sy = kBrick * kChannels, sz = kBrick * kBrick * kChannels;
-    u32x4 g[4];   // corners (x, x + 1) at (y, z), (y + 1, z), (y, z + 1), (y + 1, z + 1)
-    g[0] = load_pair(sc.bricks, ob);
-    g[1] = load_pair(sc.bricks, ob + sy);
-    g[2] = load_pair(sc.bricks, ob + sz);
-    g[3] = load_pair(sc.bricks, ob + sz + sy);
-    // texel words: lo = channels 0..3, hi = channels 4..7
+    // texel words of the 20 texels (lo = channels 0..3, hi = 4..7) and their
+    // weights: 8 grid corners, then 4 texels of each plane.  A scene without
+    // a grid (L = 0) or without planes (R = 0) leaves those weights at zero.
     uint32_t lo[20], hi[20];
     float w[20];
-    {
-        float ax = 1.0f - fx, ay = 1.0f - fy, az = 1.0f - fz;
-        float w00 = ay * az, w10 = fy * az, w01 = ay * fz, w11 = fy * fz;
-        const float wyz[4] = {w00, w10, w01, w11};
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            lo[2 * i] = g[i].x; hi[2 * i] = g[i].y; w[2 * i] = ax * wyz[i];
-            lo[2 * i + 1] = g[i].z; hi[2 * i + 1] = g[i].w; w[2 * i + 1] = fx * wyz[i];
-        }
-        // planes: (u, v) weights; u/v axes are (y, z), (x, z), (x, y)
+    for (int i = 0; i < 20; ++i) { lo[i] = 0u; hi[i] = 0u; w[i] = 0.0f; }
+    // ---- three planes: bilinear.  Their addresses depend on no load, so they
+    // are issued first and overlap the brick-index round trip below.
+    if (sc.R > 0) {
+        const float ps = (float)sc.R * 0.25f, pmax = (float)(sc.R - 1);
+        float hx = fminf(fmaxf(fmaf(p.x + 2.0f, ps, -0.5f), 0.0f), pmax);
+        float hy = fminf(fmaxf(fmaf(p.y + 2.0f, ps, -0.5f), 0.0f), pmax);
+        float hz = fminf(fmaxf(fmaf(p.z + 2.0f, ps, -0.5f), 0.0f), pmax);
+        int jx = min((int)hx, sc.R - 2), jy = min((int)hy, sc.R - 2), jz = min((int)hz, sc.R - 2);
+        float ex = hx - (float)jx, ey = hy - (float)jy, ez = hz - (float)jz;
+        const uint32_t row = (uint32_t)sc.R * kChannels, plane = (uint32_t)sc.R * row;
+        const uint32_t o0 = (uint32_t)jz * row + (uint32_t)jy * kChannels;              // P_x(y, z)
+        const uint32_t o1 = plane + (uint32_t)jz * row + (uint32_t)jx * kChannels;      // P_y(x, z)
+        const uint32_t o2 = 2u * plane + (uint32_t)jy * row + (uint32_t)jx * kChannels; // P_z(x, y)
+        u32x4 t[6];   // each = texels (u, v) and (u + 1, v)
+        t[0] = load_pair(sc.planes, o0);
+        t[1] = load_pair(sc.planes, o0 + row);
+        t[2] = load_pair(sc.planes, o1);
+        t[3] = load_pair(sc.planes, o1 + row);
+        t[4] = load_pair(sc.planes, o2);
+        t[5] = load_pair(sc.planes, o2 + row);
+        // (u, v) weights; u/v axes are (y, z), (x, z), (x, y)
         const float fu[3] = {ey, ex, ex}, fv[3] = {ez, ez, ey};
 #pragma unroll
         for (int pl = 0; pl < 3; ++pl) {
@@ -257,9 +234,41 @@ __device__ __forceinline__ void shade_sample(const DevScene &sc, float3 p, float
             lo[11 + 4 * pl] = r1.z; hi[11 + 4 * pl] = r1.w; w[11 + 4 * pl] = fu[pl] * fv[pl];
         }
     }
+    // ---- sparse 3D grid: trilinear footprint inside one apron brick.  Every
+    // index entry is a valid brick (absent blocks point at an all-zero brick),
+    // so the corner loads need no branch.
+    if (sc.L > 0) {
+        const float gs = (float)sc.L * 0.25f, gmax = (float)(sc.L - 1);
+        float gx = fminf(fmaxf(fmaf(p.x + 2.0f, gs, -0.5f), 0.0f), gmax);
+        float gy = fminf(fmaxf(fmaf(p.y + 2.0f, gs, -0.5f), 0.0f), gmax);
+        float gz = fminf(fmaxf(fmaf(p.z + 2.0f, gs, -0.5f), 0.0f), gmax);
+        int ix = min((int)gx, sc.L - 2), iy = min((int)gy, sc.L - 2), iz = min((int)gz, sc.L - 2);
+        float fx = gx - (float)ix, fy = gy - (float)iy, fz = gz - (float)iz;
+        const uint32_t bi = ((uint32_t)(iz >> 3) * sc.nbl + (uint32_t)(iy >> 3)) * sc.nbl + (uint32_t)(ix >> 3);
+        const int brick = load_at<int>(reinterpret_cast<const uint8_t *>(sc.brick_index), bi * 4u);
+        const uint32_t ob = (uint32_t)brick * kBrickBytes +
+                            (uint32_t)((((iz & 7) * kBrick + (iy & 7)) * kBrick + (ix & 7)) * kChannels);
+        constexpr uint32_t sy = kBrick * kChannels, sz = kBrick * kBrick * kChannels;
+        u32x4 g[4];   // corners (x, x + 1) at (y, z), (y + 1, z), (y, z + 1), (y + 1, z + 1)
+        g[0] = load_pair(sc.bricks, ob);
+        g[1] = load_pair(sc.bricks, ob + sy);
+        g[2] = load_pair(sc.bricks, ob + sz);
+        g[3] = load_pair(sc.bricks, ob + sz + sy);
+        float ax = 1.0f - fx, ay = 1.0f - fy, az = 1.0f - fz;
+        float w00 = ay * az, w10 = fy * az, w01 = ay * fz, w11 = fy * fz;
+        const float wyz[4] = {w00, w10, w01, w11};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            lo[2 * i] = g[i].x; hi[2 * i] = g[i].y; w[2 * i] = ax * wyz[i];
+            lo[2 * i + 1] = g[i].z; hi[2 * i + 1] = g[i].w; w[2 * i + 1] = fx * wyz[i];
+        }
+    }
+    // number of sources whose weights sum to one
+    const float nsrc = (sc.L > 0 ? 1.0f : 0.0f) + (sc.R > 0 ? 3.0f : 0.0f);
     // ---- Eq. 8 dequantises each code affinely, q(b) = a b - m with a = 2m/255,
-    // and the 20 weights form four partitions of unity (one per source), so
-    // sum_i w_i q(b_i) = a * sum_i w_i b_i - 4m exactly.  The FP32 path
+    // and the weights of each present source sum to one, so
+    // sum_i w_i q(b_i) = a * sum_i w_i b_i - n m exactly (n sources: 4 for
+    // grid + planes).  The FP32 path
     // (kFeatF16 = false) interpolates the codes and applies the affine map
     // once per channel: the same real number with one convert and one FMA per
     // texel and channel; the two FP32 evaluations differ by rounding only
@@ -276,7 +285,7 @@ __device__ __forceinline__ void shade_sample(const DevScene &sc, float3 p, float
     } else {
 #pragma unroll
         for (int i = 0; i < 20; ++i) s0 = fmaf(w[i], (float)byte_of(lo[i], 0), s0);
-        s0 = fmaf(s0, md * (2.0f / 255.0f), -4.0f * md);
+        s0 = fmaf(s0, md * (2.0f / 255.0f), -nsrc * md);
     }
     float tau = __expf(s0);                       // Eq. 6
     float trans = __expf(-tau * delta);           // e^{-tau delta} = 1 - alpha (Eq. 1)
@@ -305,7 +314,7 @@ __device__ __forceinline__ void shade_sample(const DevScene &sc, float3 p, float
                 for (int c = 0; c < 4; ++c) s[3 + c] = fmaf(w[i], (float)byte_of(hi[i], c), s[3 + c]);
             }
 #pragma unroll
-            for (int c = 0; c < 7; ++c) s[c] = fmaf(s[c], af, -4.0f * mf);
+            for (int c = 0; c < 7; ++c) s[c] = fmaf(s[c], af, -nsrc * mf);
         }
         float wt = acc.T * alpha;                 // Eq. 1-2
         acc.cd0 = fmaf(wt, sigmoid(s[0]), acc.cd0);

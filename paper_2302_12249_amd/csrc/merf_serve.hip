@@ -365,7 +365,7 @@ int merf_server_submit(merf_server_t S, int32_t scene_id, const merf_camera *cam
         if (it == S->scenes.end()) return fail(MERF_E_INVALID, "unknown scene %d", scene_id);
         const DevScene *ds = scene_dev(it->second.h);
         Request r;
-        if ((rc = check_params(p, ds ? ds->R : 1, &r.step))) return rc;
+        if ((rc = check_params(p, ds ? std::max(ds->R, ds->L) : 1, &r.step))) return rc;
         r.scene = scene_id;
         r.cam = *cam;
         r.p = *p;

@@ -53,7 +53,7 @@ class merf_render_params(C.Structure):
 
 
 EXPORTS = ["merf_scene_upload", "merf_render", "merf_free", "merf_last_error", "merf_set_hbm_budget",
-           "merf_hbm_in_use", "merf_scene_bytes", "merf_dequantize"]
+           "merf_hbm_in_use", "merf_scene_bytes", "merf_dequantize", "merf_occupancy_pyramid"]
 
 _lib = None
 
@@ -83,6 +83,9 @@ def load(path: str = LIB_PATH):
     lib.merf_scene_bytes.restype = C.c_size_t
     lib.merf_dequantize.argtypes = [C.c_void_p, C.c_int64, C.c_float, C.c_int32, C.c_void_p, C.c_void_p]
     lib.merf_dequantize.restype = C.c_int
+    lib.merf_occupancy_pyramid.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_int32,
+                                           C.POINTER(C.c_void_p), C.c_void_p]
+    lib.merf_occupancy_pyramid.restype = C.c_int
     _lib = lib
     return lib
 
@@ -191,6 +194,21 @@ def merf_render(handle: int, cam_arr, n_cams: int, params: merf_render_params, o
 def merf_dequantize(codes_ptr: int, n: int, m: float, prec: int, out_ptr: int, stream_ptr: int = 0):
     _check(load().merf_dequantize(C.c_void_p(codes_ptr), int(n), float(m), int(prec), C.c_void_p(out_ptr),
                                   C.c_void_p(stream_ptr)))
+
+
+def occupancy_pyramid(mask, factors, stream=None):
+    """Max-pool a cubic device mask (torch uint8 [r, r, r]) by each factor; returns
+    a list of torch uint8 tensors [r/f, r/f, r/f] (merf_occupancy_pyramid)."""
+    import torch
+    r = int(mask.shape[0])
+    assert mask.is_cuda and mask.dtype == torch.uint8 and mask.is_contiguous() and tuple(mask.shape) == (r, r, r)
+    outs = [torch.empty((r // f,) * 3, dtype=torch.uint8, device=mask.device) for f in factors]
+    fac = (C.c_int32 * len(factors))(*[int(f) for f in factors])
+    ptrs = (C.c_void_p * len(factors))(*[o.data_ptr() for o in outs])
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(load().merf_occupancy_pyramid(C.c_void_p(mask.data_ptr()), r, fac, len(factors), ptrs,
+                                         C.c_void_p(st.cuda_stream)))
+    return outs
 
 
 class Renderer:

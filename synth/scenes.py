@@ -228,7 +228,24 @@ def make_scene(L: int, R: int, frac: float, extent: float, r_lo: float, r_hi: fl
     mrng = np.random.default_rng(seed + 1000 if mlp_seed is None else mlp_seed)
     mlp = mrng.normal(0.0, 0.1, size=mlp_param_count()).astype(np.float32)
     return Scene(name=name, seed=seed, L=L, R=R, block_index=block_index, blocks=blocks,
-                 planes=planes, occ=occ, mlp=mlp, step=4.0 / R)
+                 planes=planes, occ=occ, mlp=mlp, step=4.0 / max(R, L))
+
+
+def planes_only(scene: Scene) -> Scene:
+    """The same scene without its 3D grid (L = 0): the paper's ablation of MERF
+    without the low-resolution voxel grid (Sec. 7)."""
+    return dataclasses.replace(scene, name=scene.name + "-planes", L=0,
+                               block_index=np.zeros(0, np.int32),
+                               blocks=np.zeros((0, BLOCK, BLOCK, BLOCK, CHANNELS), np.uint8))
+
+
+def grid_only_scene(L: int, frac: float, seed: int, extent: float = 1.99, r_lo: float = 0.05,
+                    r_hi: float = 0.25, mlp_seed: Optional[int] = None) -> Scene:
+    """A block-sparse grid with no planes (R = 0), e.g. a high-resolution grid in
+    the spirit of the paper's SNeRG++ comparison."""
+    sc = make_scene(L, 0, frac, extent, r_lo, r_hi, pools=(8, 2, 1), seed=seed, mlp_seed=mlp_seed,
+                    name=f"grid{L}")
+    return sc
 
 
 def preset_scene(name: str, seed: Optional[int] = None) -> Scene:

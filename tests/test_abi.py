@@ -151,3 +151,24 @@ def test_dequantize_argument_checks():
     assert lib.merf_dequantize(None, 0, 7.0, 0, None, None) == merf.MERF_OK
     assert lib.merf_dequantize(C.c_void_p(16), 4, 7.0, 3, C.c_void_p(16), None) == merf.MERF_E_INVALID
     assert lib.merf_dequantize(C.c_void_p(16), 4, -1.0, 0, C.c_void_p(16), None) == merf.MERF_E_INVALID
+
+
+def test_occupancy_pyramid_argument_checks():
+    lib = merf.load()
+    fac = (C.c_int32 * 2)(4, 3)
+    ptrs = (C.c_void_p * 2)(16, 16)
+    assert lib.merf_occupancy_pyramid(C.c_void_p(16), 16, fac, 2, ptrs, None) == merf.MERF_E_INVALID  # 3 does not divide 16
+    assert lib.merf_occupancy_pyramid(C.c_void_p(16), 0, fac, 1, ptrs, None) == merf.MERF_E_INVALID
+    assert lib.merf_occupancy_pyramid(None, 16, fac, 1, ptrs, None) == merf.MERF_E_INVALID
+
+
+def test_representation_variants_validate():
+    lib = merf.load()
+    sc = synth.preset_scene("tiny")
+    d, keep = merf.scene_desc(sc)
+    h = C.c_void_p()
+    d.grid_res = 0                              # planes only, but blocks still given
+    assert lib.merf_scene_upload(C.byref(d), C.byref(h)) == merf.MERF_E_INVALID
+    d.num_blocks = 0
+    d.plane_res = 0                             # neither grid nor planes
+    assert lib.merf_scene_upload(C.byref(d), C.byref(h)) == merf.MERF_E_INVALID

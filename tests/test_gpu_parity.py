@@ -287,3 +287,19 @@ def test_fp16_features_full_sampled(torch, merf, full_scene):
     ok = st["fragile"] == 0
     say(f"full feat f16: PSNR {p:.2f} dB  max|err| non-fragile {np.abs(gpu[sel] - ref)[ok].max():.3e}")
     assert p >= 45.0
+
+
+def test_planes_only_variant(torch, merf, tiny_scene, tiny_cams):
+    say("tiny scene without its 3D grid (planes only)")
+    po = synth.planes_only(tiny_scene)
+    gpu = gpu_render(torch, merf, po, tiny_cams)
+    ref, st = oracle.render(po, tiny_cams)
+    check(gpu, ref, st["fragile"], "planes only")
+
+
+def test_grid_only_variant(torch, merf, tiny_cams):
+    say("grid-only scene (L = 128, no planes)")
+    go = synth.grid_only_scene(128, 0.08, seed=4)
+    gpu = gpu_render(torch, merf, go, tiny_cams)
+    ref, st = oracle.render(go, tiny_cams)
+    check(gpu, ref, st["fragile"], "grid only")

@@ -152,3 +152,34 @@ def test_mlp_matches_numpy(tiny_scene):
         h2 = np.maximum(h1 @ W1 + b1, 0)
         y = h2 @ W2 + b2
         assert np.allclose(oracle.mlp(tiny_scene, x), y, atol=1e-13)
+
+
+def test_planes_only_and_grid_only_sum_their_sources():
+    """Without the 3D grid (the paper's Sec. 7 ablation) t = P_x + P_y + P_z;
+    without planes t = V: constant bytes give 3 q(b) and q(b)."""
+    import dataclasses
+    import synth
+    sc = dense_scene(L=16, R=16, fill_grid=lambda z, y, x, c: 40 + 0 * x, fill_planes=lambda pl, v, u, c: 200 + 0 * u)
+    po = synth.planes_only(sc)
+    go = dataclasses.replace(sc, R=0, planes=np.zeros((3, 0, 0, 8), np.uint8))
+    rng = np.random.default_rng(8)
+    for p in rng.uniform(-2, 2, (50, 3)):
+        t = oracle.features(po, p)
+        assert abs(t[0] - 3 * float(dequant_exact(200, 14))) < 1e-12
+        assert abs(t[6] - 3 * float(dequant_exact(200, 7))) < 1e-12
+        t = oracle.features(go, p)
+        assert abs(t[0] - float(dequant_exact(40, 14))) < 1e-12
+        assert abs(t[2] - float(dequant_exact(40, 7))) < 1e-12
+
+
+def test_planes_only_reproduces_plane_ramp():
+    import synth
+    R = 32
+    fp = lambda pl, v, u, c: np.where(pl == 1, 10 + 5 * u + 2 * v, 100) + 0 * c
+    po = synth.planes_only(dense_scene(L=16, R=R, fill_planes=fp))
+    rng = np.random.default_rng(9)
+    for p in rng.uniform(-2 + 2.0 / R, 2 - 2.0 / R, (100, 3)):
+        g = (p + 2.0) * R / 4.0 - 0.5
+        t = oracle.features(po, p)
+        want = deq(10 + 5 * g[0] + 2 * g[2], 14) + 2 * deq(100, 14)   # P_y(x, z) plus two constant planes
+        assert abs(t[0] - want) < 1e-11
