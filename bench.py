@@ -31,7 +31,10 @@ METRIC = "rays/sec (Mrays/s) at 1080p, % HBM roofline; p50/p99 frame latency ser
 # 4 B brick index; per sample with alpha != 0 another 20 x 7 appearance codes;
 # 1 B per occupancy lookup; 16 B of output per ray.
 B_EVAL, B_CONTRIB, B_OCC, B_RAY = 24, 140, 1, 16
-KERNEL_SOURCES = ["paper_2302_12249_amd/csrc/merf_render.hip", "paper_2302_12249_amd/csrc/merf_device.h"]
+# everything that decides what the render kernel reads and how (kernel, scene
+# layout, brick packing); counters taken on other sources are stale
+KERNEL_SOURCES = ["paper_2302_12249_amd/csrc/merf_render.hip", "paper_2302_12249_amd/csrc/merf_device.h",
+                  "paper_2302_12249_amd/csrc/merf_api.hip", "paper_2302_12249_amd/csrc/merf_ingest.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_full_1080p_traffic.json")
 
 
