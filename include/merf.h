@@ -58,7 +58,9 @@ typedef struct merf_scene *merf_scene_t;
  *                  plane 1 = P_y indexed [z][x], plane 2 = P_z indexed [y][x].
  *  occ_levels      number of occupancy levels, 1..4, coarse to fine.
  *  occ_res[l]      level resolution r; a cell covers a box of edge 4/r of the
- *                  contracted domain [-2, 2]^3.
+ *                  contracted domain [-2, 2]^3.  Each resolution divides the
+ *                  next finer one (a max-pool pyramid, Sec. 6).  A sample is
+ *                  rendered only if every level marks the cell containing it.
  *  occ[l]          uint8 [r^3] z-major, nonzero = occupied.
  *  m_density,
  *  m_feature       Eq. 8 ranges: code b means 2 m b / 255 - m (14 and 7).
@@ -109,8 +111,15 @@ typedef struct {
     int32_t mlp_prec;                     /* deferred MLP: 0 = fp32, 1 = fp16, 2 = bf16 */
     int32_t feat_prec;                    /* 0 = codes interpolated in fp32; 1 = every code
                                              dequantised to float16 first (sums stay fp32) */
+    int32_t skip_mode;                    /* empty-space skipping, same image either way:
+                                             0 = distance grid derived from the occupancy
+                                             levels at upload (the largest empty cube around
+                                             a sample is left in one step);
+                                             1 = the levels themselves, coarse to fine,
+                                             leaving one empty cell per step (Sec. 6) */
     uint64_t *stats_dev;                  /* NULL, or device uint64[8] to which the render
-                                             ADDS: [0] rays, [1] occupancy lookups,
+                                             ADDS: [0] rays, [1] occupancy lookups
+                                             (skip_mode 0: distance-grid lookups),
                                              [2] lattice samples visited, [3] samples
                                              evaluated, [4] samples with alpha > 0,
                                              [5] rays terminated early, [6..7] 0 */
@@ -120,7 +129,9 @@ typedef struct {
  * Copy a baked scene into device memory and return its handle.
  * desc and every array it points to are host memory, read during the call.
  * The library re-lays the data out for the GPU (sparse grid blocks padded
- * with a one-voxel apron so a trilinear footprint never spans two blocks).
+ * with a one-voxel apron so a trilinear footprint never spans two blocks)
+ * and derives the empty-space distance grid of skip_mode 0 (one byte per
+ * cell of the finest occupancy level).
  * Synchronous: the scene is resident when the call returns.
  * Errors: MERF_E_INVALID for an inconsistent descriptor (sizes, block index
  * entries out of range, NULL arrays); MERF_E_OOM when the device bytes would
@@ -185,6 +196,25 @@ int merf_dequantize(const uint8_t *codes_dev, int64_t n, float m, int32_t prec, 
  */
 int merf_occupancy_pyramid(const uint8_t *mask_dev, int32_t res, const int32_t *factors, int32_t n_levels,
                            uint8_t *const *out_dev, void *hip_stream);
+
+/*
+ * Empty-space distance grid: the acceleration structure behind skip_mode 0 of
+ * merf_render, derived from the occupancy hierarchy of Sec. 6 (the upload
+ * builds it itself; this entry point exposes the same routine).
+ * occ_dev[l] (device, res[l]^3 bytes, z-major, nonzero = occupied) for
+ * l = 0 .. n_levels - 1, coarse to fine, each res[l] dividing res[l + 1].
+ * out_dev (device, r^3 bytes, r = res[n_levels - 1], caller-owned) receives
+ * for every cell of the finest level the Chebyshev distance, in cells, to the
+ * nearest cell that every level marks occupied, capped at 255; 0 means the
+ * cell itself is occupied at every level, 255 also means no such cell.  Host
+ * arrays occ_dev and res are read during the call.  Allocates 2 r^3 bytes of
+ * device scratch, runs on hip_stream and returns once the grid is complete.
+ * Errors: MERF_E_INVALID for n_levels outside [1, 4], a resolution outside
+ * [1, 1024] or not dividing the next, or NULL buffers; MERF_E_OOM if the
+ * scratch cannot be allocated.
+ */
+int merf_distance_grid(const uint8_t *const *occ_dev, const int32_t *res, int32_t n_levels, uint8_t *out_dev,
+                       void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -91,6 +91,11 @@ int validate_desc(const merf_scene_desc *d) {
         if (d->occ_res[l] < 1 || d->occ_res[l] > 1024)
             return fail(MERF_E_INVALID, "occ_res[%d] = %d must be in [1, 1024]", l, d->occ_res[l]);
         if (!d->occ[l]) return fail(MERF_E_INVALID, "occ[%d] is NULL", l);
+        // coarse to fine, each level refining the previous one (a max-pool
+        // pyramid), so every cell of the finest level lies in one cell of each
+        if (l > 0 && d->occ_res[l] % d->occ_res[l - 1] != 0)
+            return fail(MERF_E_INVALID, "occ_res[%d] = %d is not a multiple of occ_res[%d] = %d", l, d->occ_res[l],
+                        l - 1, d->occ_res[l - 1]);
     }
     if (!(d->m_density > 0.0f) || !(d->m_feature > 0.0f) || !std::isfinite(d->m_density) ||
         !std::isfinite(d->m_feature))
@@ -135,14 +140,16 @@ int64_t count_bricks(const merf_scene_desc *d) {
 
 // Offsets of the arrays inside a scene's single device allocation.
 struct Layout {
-    size_t bidx, bricks, planes, occ[kMaxLevels], mlp, total;
+    size_t bidx, bricks, planes, occ[kMaxLevels], dist, mlp, total;
 };
 
+// A scene without a grid gets a one-entry index (pointing at the zero brick);
+// one without planes gets zero 2x2 stand-in planes.
 Layout make_layout(const merf_scene_desc *d, int64_t nbricks) {
-    const size_t nbl = (size_t)(d->grid_res / kBlock), R = (size_t)d->plane_res;
+    const size_t nbl = (size_t)(d->grid_res / kBlock), R = d->plane_res > 0 ? (size_t)d->plane_res : 2;
     Layout o{};
     size_t off = 0;
-    o.bidx = off; off = align_up(off + nbl * nbl * nbl * sizeof(int32_t), 256);
+    o.bidx = off; off = align_up(off + std::max<size_t>(nbl * nbl * nbl, 1) * sizeof(int32_t), 256);
     o.bricks = off; off = align_up(off + (size_t)(nbricks + 1) * kBrickBytes, 256);
     o.planes = off; off = align_up(off + 3 * R * R * kChannels, 256);
     for (int l = 0; l < d->occ_levels; ++l) {
@@ -150,6 +157,8 @@ Layout make_layout(const merf_scene_desc *d, int64_t nbricks) {
         o.occ[l] = off;
         off = align_up(off + r * r * r, 256);
     }
+    const size_t rf = (size_t)d->occ_res[d->occ_levels - 1];
+    o.dist = off; off = align_up(off + rf * rf * rf, 256);
     o.mlp = off; off = align_up(off + kMlpParams * sizeof(float), 256);
     o.total = off;
     return o;
@@ -181,6 +190,7 @@ void assign_bricks(const merf_scene_desc *d, std::vector<int32_t> &bidx, std::ve
     const int32_t zero = (int32_t)pos.size();
     for (int32_t &b : bidx)
         if (b < 0) b = zero;
+    if (bidx.empty()) bidx.push_back(zero);   // stand-in grid of a planes-only scene
 }
 
 }  // namespace
@@ -204,6 +214,7 @@ int check_params(const merf_render_params *p, int res, float *step_out) {
     if (p->delta_mode != 0 && p->delta_mode != 1) return fail(MERF_E_INVALID, "delta_mode %d", p->delta_mode);
     if (p->mlp_prec < 0 || p->mlp_prec > 2) return fail(MERF_E_INVALID, "mlp_prec %d not in {0, 1, 2}", p->mlp_prec);
     if (p->feat_prec != 0 && p->feat_prec != 1) return fail(MERF_E_INVALID, "feat_prec %d not in {0, 1}", p->feat_prec);
+    if (p->skip_mode != 0 && p->skip_mode != 1) return fail(MERF_E_INVALID, "skip_mode %d not in {0, 1}", p->skip_mode);
     *step_out = step;
     return MERF_OK;
 }
@@ -226,6 +237,7 @@ void begin_batch(RenderBatch &rb, const merf_render_params &p, float step) {
     rb.delta_mode = p.delta_mode;
     rb.mlp_prec = p.mlp_prec;
     rb.feat_prec = p.feat_prec;
+    rb.skip_mode = p.skip_mode;
     rb.stats = reinterpret_cast<unsigned long long *>(p.stats_dev);
 }
 
@@ -299,7 +311,9 @@ int merf_scene_upload(const merf_scene_desc *desc, merf_scene_t *out) {
     const size_t raw_blocks = (size_t)desc->num_blocks * kBlock * kBlock * kBlock * kChannels;
     const size_t s_blocks = 0, s_index = align_up(std::max<size_t>(raw_blocks, 8), 256),
                  s_pos = s_index + align_up((size_t)nbl * nbl * nbl * sizeof(int32_t), 256),
-                 staging = s_pos + align_up(std::max<size_t>(bpos.size(), 1) * sizeof(int32_t), 256);
+                 s_dist0 = s_pos + align_up(std::max<size_t>(bpos.size(), 1) * sizeof(int32_t), 256);
+    const size_t rf = (size_t)desc->occ_res[desc->occ_levels - 1], nf = rf * rf * rf;
+    const size_t s_dist1 = s_dist0 + align_up(nf, 256), staging = s_dist1 + align_up(nf, 256);
     void *base = nullptr, *stage = nullptr;
     hipError_t e = hipMalloc(&base, total);
     if (e == hipSuccess) e = hipMalloc(&stage, staging);
@@ -329,9 +343,19 @@ int merf_scene_upload(const merf_scene_desc *desc, merf_scene_t *out) {
         e = hipMemcpy(c.dst, c.src, c.n, hipMemcpyHostToDevice);
         if (e != hipSuccess) break;
     }
+    if (e == hipSuccess && R == 0) e = hipMemset(dev(o_planes), 0, (size_t)3 * 2 * 2 * kChannels);
     if (e == hipSuccess)
         e = launch_pack_bricks(stg(s_blocks), reinterpret_cast<const int32_t *>(stg(s_index)),
                                reinterpret_cast<const int32_t *>(stg(s_pos)), (int)nbricks, L, dev(o_bricks), nullptr);
+    if (e == hipSuccess) {
+        OccLevels lv{};
+        lv.n = desc->occ_levels;
+        for (int l = 0; l < lv.n; ++l) {
+            lv.occ[l] = dev(o_occ[l]);
+            lv.res[l] = desc->occ_res[l];
+        }
+        e = launch_distance_grid(lv, stg(s_dist0), stg(s_dist1), dev(lay.dist), nullptr);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     (void)hipFree(stage);
     if (e != hipSuccess) {
@@ -354,10 +378,15 @@ int merf_scene_upload(const merf_scene_desc *desc, merf_scene_t *out) {
         ds.occ_res[l] = l < desc->occ_levels ? desc->occ_res[l] : 1;
         ds.occ_cell[l] = 4.0f / (float)ds.occ_res[l];
     }
+    ds.dist = dev(lay.dist);
+    ds.dist_res = (int32_t)rf;
+    ds.dist_cell = 4.0f / (float)rf;
     ds.mlp = reinterpret_cast<const float *>(dev(o_mlp));
-    ds.L = L;
-    ds.R = R;
-    ds.nbl = nbl;
+    ds.L = L > 0 ? L : kBlock;            // stand-ins, see DevScene
+    ds.R = R > 0 ? R : 2;
+    ds.nbl = L > 0 ? nbl : 1;
+    ds.nsrc = (L > 0 ? 1.0f : 0.0f) + (R > 0 ? 3.0f : 0.0f);
+    ds.res = std::max(L, R);
     ds.occ_levels = desc->occ_levels;
     ds.m_density = desc->m_density;
     ds.m_feature = desc->m_feature;
@@ -394,7 +423,7 @@ int merf_render(merf_scene_t s, const merf_camera *cams, int32_t n_cams, const m
     clear_error();
     if (!live(s)) return fail(MERF_E_INVALID, "merf_render: invalid scene handle");
     float step = 0.0f;
-    int rc = check_params(p, std::max(s->ds.R, s->ds.L), &step);
+    int rc = check_params(p, s->ds.res, &step);
     if (rc) return rc;
     if (n_cams < 0) return fail(MERF_E_INVALID, "n_cams %d < 0", n_cams);
     if (n_cams == 0) return MERF_OK;
@@ -446,6 +475,38 @@ int merf_occupancy_pyramid(const uint8_t *mask_dev, int32_t res, const int32_t *
         hipError_t e = launch_maxpool(mask_dev, res, factors[l], out_dev[l], stream);
         if (e != hipSuccess) return hip_fail(e, "max-pool launch");
     }
+    return MERF_OK;
+}
+
+int merf_distance_grid(const uint8_t *const *occ_dev, const int32_t *res, int32_t n_levels, uint8_t *out_dev,
+                       void *hip_stream) {
+    clear_error();
+    if (n_levels < 1 || n_levels > kMaxLevels)
+        return fail(MERF_E_INVALID, "n_levels %d not in [1, %d]", n_levels, kMaxLevels);
+    if (!occ_dev || !res || !out_dev) return fail(MERF_E_INVALID, "NULL buffer");
+    OccLevels lv{};
+    lv.n = n_levels;
+    for (int l = 0; l < n_levels; ++l) {
+        if (res[l] < 1 || res[l] > kMaxDistRes) return fail(MERF_E_INVALID, "res[%d] = %d not in [1, %d]", l, res[l], kMaxDistRes);
+        if (l > 0 && res[l] % res[l - 1] != 0)
+            return fail(MERF_E_INVALID, "res[%d] = %d is not a multiple of res[%d] = %d", l, res[l], l - 1, res[l - 1]);
+        if (!occ_dev[l]) return fail(MERF_E_INVALID, "occ_dev[%d] is NULL", l);
+        lv.occ[l] = occ_dev[l];
+        lv.res[l] = res[l];
+    }
+    const size_t r = (size_t)res[n_levels - 1], n = r * r * r;
+    void *tmp = nullptr;
+    hipError_t e = hipMalloc(&tmp, 2 * align_up(n, 256));
+    if (e != hipSuccess || !tmp) {
+        (void)hipGetLastError();
+        return fail(MERF_E_OOM, "hipMalloc of %zu scratch bytes failed", 2 * align_up(n, 256));
+    }
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    uint8_t *t0 = static_cast<uint8_t *>(tmp), *t1 = t0 + align_up(n, 256);
+    e = launch_distance_grid(lv, t0, t1, out_dev, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return hip_fail(e, "distance grid");
     return MERF_OK;
 }
 

@@ -19,6 +19,7 @@ constexpr int kMlpParams = kMlpIn * kMlpHidden + kMlpHidden + kMlpHidden * kMlpH
                            kMlpHidden * kMlpOut + kMlpOut;
 constexpr int kTile = 8;                         // a wave renders an 8x8 pixel tile
 constexpr int kCamsPerLaunch = 16;               // cameras carried in one launch's arguments
+constexpr int kMaxDistRes = 1024;                // finest occupancy resolution (distance grid)
 
 // Scene as laid out in device memory.
 //   brick_index  int32 [(L/8)^3] z-major: brick slot; blocks whose brick would
@@ -27,18 +28,33 @@ constexpr int kCamsPerLaunch = 16;               // cameras carried in one launc
 //                axis, so the 2x2x2 trilinear footprint whose low corner lies
 //                in block b is inside brick b.
 //   planes       uint8 [3][R][R][8]: P_x[z][y], P_y[z][x], P_z[y][x].
-//   occ[l]       uint8 [r^3] z-major, coarse to fine.
+//   occ[l]       uint8 [r^3] z-major, coarse to fine; each resolution divides
+//                the next finer one.
+//   dist         uint8 [r_f^3] z-major at the finest resolution r_f: Chebyshev
+//                distance, in cells, from the cell to the nearest cell whose
+//                every level is occupied (0 = the cell is occupied at every
+//                level; capped at 255).  Cells within distance D - 1 of a
+//                cell with value D are all empty.
 //   mlp          float32 W0[34][16] b0 W1[16][16] b1 W2[16][3] b2.
+// A scene without a grid carries a stand-in grid (L = 8, one index entry
+// pointing at the zero brick); a scene without planes carries all-zero 2x2
+// stand-in planes (R = 2).  Stand-ins read code 0, and nsrc counts only the
+// present sources, so the kernels gather both kinds without branching.
 struct DevScene {
     const int32_t *brick_index;
     const uint8_t *bricks;
     const uint8_t *planes;
     const uint8_t *occ[kMaxLevels];
+    const uint8_t *dist;
     const float *mlp;
     int32_t L, R, nbl, occ_levels;
     int32_t occ_res[kMaxLevels];
     float occ_cell[kMaxLevels];                  // cell edge 4 / r of each level
+    int32_t dist_res;                            // r_f
+    float dist_cell;                             // 4 / r_f
     float m_density, m_feature;
+    float nsrc;                                  // present sources: grid 1 + planes 3
+    int32_t res;                                 // finest present resolution max(L, R) of the scene
 };
 
 struct DevCamera {
@@ -52,7 +68,7 @@ struct DevCamera {
 struct RenderBatch {
     int32_t n_cams, total_tiles;
     float step, inv_step, t_min;
-    int32_t delta_mode, mlp_prec, feat_prec;
+    int32_t delta_mode, mlp_prec, feat_prec, skip_mode;
     unsigned long long *stats;
     DevCamera cams[kCamsPerLaunch];
 };
@@ -68,5 +84,14 @@ hipError_t launch_dequant(const uint8_t *codes, int64_t n, float m, int prec, vo
 hipError_t launch_pack_bricks(const uint8_t *blocks, const int32_t *block_index, const int32_t *brick_pos,
                               int nbricks, int L, uint8_t *bricks, hipStream_t stream);
 hipError_t launch_maxpool(const uint8_t *in, int rin, int f, uint8_t *out, hipStream_t stream);
+// Distance grid of DevScene::dist from the occupancy levels (tmp0, tmp1:
+// scratch of r_f^3 bytes each).
+struct OccLevels {
+    const uint8_t *occ[kMaxLevels];
+    int32_t res[kMaxLevels];
+    int32_t n;
+};
+hipError_t launch_distance_grid(const OccLevels &lv, uint8_t *tmp0, uint8_t *tmp1, uint8_t *dist,
+                                hipStream_t stream);
 
 }  // namespace merf

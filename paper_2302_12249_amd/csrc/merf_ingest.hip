@@ -2,7 +2,8 @@
 // apron bricks, and max-pooling of a binary occupancy mask into the coarser
 // levels of the empty-space hierarchy (Sec. 6 builds its occupancy grids by
 // max-pooling the full-resolution mask; Sec. 5.3 stores the grid in a
-// block-sparse format).
+// block-sparse format); and the empty-space distance grid the renderer skips
+// with, derived from the occupancy levels.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -57,6 +58,50 @@ __global__ void k_maxpool(const uint8_t *__restrict__ in, int rin, int f, uint8_
     out[gid] = any ? 1 : 0;
 }
 
+// Empty-space distance grid, step 1: the cell of the finest level is
+// occupied when every level marks the cell containing it (the levels nest,
+// so each finest cell lies in one cell of every level).  Output is the seed
+// of the distance transform: 0 for occupied, 255 for empty.
+__global__ void k_occ_combine(const OccLevels lv, uint8_t *__restrict__ out) {
+    const int rf = lv.res[lv.n - 1];
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)rf * rf * rf) return;
+    const int x = (int)(gid % rf), y = (int)((gid / rf) % rf), z = (int)(gid / ((int64_t)rf * rf));
+    bool occ = true;
+    for (int l = 0; l < lv.n && occ; ++l) {
+        const int r = lv.res[l], k = rf / r;
+        occ = lv.occ[l][((size_t)(z / k) * r + (y / k)) * r + (x / k)] != 0;
+    }
+    out[gid] = occ ? 0 : 255;
+}
+
+// Step 2, one pass per axis: the Chebyshev (L-infinity) distance to the
+// nearest occupied cell is separable,
+//   d(c) = min over cells t of the line through c along the axis of
+//          max(|c_a - t_a|, d_prev(t)),
+// starting from the seed and applied along x, then y, then z; values are
+// capped at 255 (a cap only shortens skips).  One workgroup per line, the
+// line staged in LDS; each cell scans outwards and stops once the offset
+// reaches its best distance.
+__global__ void k_dist_axis(const uint8_t *__restrict__ in, uint8_t *__restrict__ out, int r, int axis) {
+    __shared__ uint8_t line[kMaxDistRes];
+    const int64_t lid = blockIdx.x;
+    int64_t base, stride;
+    if (axis == 0) { base = lid * r; stride = 1; }
+    else if (axis == 1) { base = (lid / r) * r * r + lid % r; stride = r; }
+    else { base = lid; stride = (int64_t)r * r; }
+    for (int c = (int)threadIdx.x; c < r; c += (int)blockDim.x) line[c] = in[base + c * stride];
+    __syncthreads();
+    for (int c = (int)threadIdx.x; c < r; c += (int)blockDim.x) {
+        int best = line[c];
+        for (int dd = 1; dd < best; ++dd) {
+            if (c - dd >= 0) best = min(best, max(dd, (int)line[c - dd]));
+            if (c + dd < r) best = min(best, max(dd, (int)line[c + dd]));
+        }
+        out[base + c * stride] = (uint8_t)best;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_pack_bricks(const uint8_t *blocks, const int32_t *block_index, const int32_t *brick_pos,
@@ -65,6 +110,19 @@ hipError_t launch_pack_bricks(const uint8_t *blocks, const int32_t *block_index,
     const int64_t grid = (total + 255) / 256;
     hipLaunchKernelGGL(k_pack_bricks, dim3((unsigned)grid), dim3(256), 0, stream, blocks, block_index, brick_pos,
                        nbricks, L, L / kBlock, bricks);
+    return hipGetLastError();
+}
+
+hipError_t launch_distance_grid(const OccLevels &lv, uint8_t *tmp0, uint8_t *tmp1, uint8_t *dist,
+                                hipStream_t stream) {
+    const int r = lv.res[lv.n - 1];
+    const int64_t n = (int64_t)r * r * r;
+    if (n <= 0 || r > kMaxDistRes) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_occ_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, lv, tmp0);
+    const dim3 lines((unsigned)((int64_t)r * r)), block(256);
+    hipLaunchKernelGGL(k_dist_axis, lines, block, 0, stream, tmp0, tmp1, r, 0);
+    hipLaunchKernelGGL(k_dist_axis, lines, block, 0, stream, tmp1, tmp0, r, 1);
+    hipLaunchKernelGGL(k_dist_axis, lines, block, 0, stream, tmp0, dist, r, 2);
     return hipGetLastError();
 }
 

@@ -181,13 +181,76 @@ __device__ __forceinline__ T load_at(const uint8_t *base, uint32_t off) {
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-// 16-byte load (two adjacent 8-byte texels) that stays one instruction: the
-// empty asm consumes the whole vector, so the compiler cannot split it into
-// per-word loads and sink the appearance words behind the alpha test.
+// 16-byte load: two adjacent 8-byte texels.
 __device__ __forceinline__ u32x4 load_pair(const uint8_t *base, uint32_t off) {
-    u32x4 v = *reinterpret_cast<const u32x4 *>(base + off);
-    asm volatile("" : "+v"(v));
-    return v;
+    return *reinterpret_cast<const u32x4 *>(base + off);
+}
+
+// Byte offsets of the 20 texels one sample reads.  Planes: the (u, v) and
+// (u + 1, v) texels of row v start at op[p] and those of row v + 1 at
+// op[p] + prow.  Grid: the 2x2x2 footprint of brick slot brick_index[bi]
+// starts at byte ol of that brick.
+struct Footprint {
+    uint32_t op[3], prow, bi, ol;
+    float ex, ey, ez;   // plane texel fractions
+    float fx, fy, fz;   // grid voxel fractions
+};
+
+__device__ __forceinline__ Footprint footprint(const DevScene &sc, float3 p) {
+    Footprint f;
+    // ---- three planes, bilinear: P_x(y, z), P_y(x, z), P_z(x, y)
+    const float ps = (float)sc.R * 0.25f, pmax = (float)(sc.R - 1);
+    float hx = fminf(fmaxf(fmaf(p.x + 2.0f, ps, -0.5f), 0.0f), pmax);
+    float hy = fminf(fmaxf(fmaf(p.y + 2.0f, ps, -0.5f), 0.0f), pmax);
+    float hz = fminf(fmaxf(fmaf(p.z + 2.0f, ps, -0.5f), 0.0f), pmax);
+    int jx = min((int)hx, sc.R - 2), jy = min((int)hy, sc.R - 2), jz = min((int)hz, sc.R - 2);
+    f.ex = hx - (float)jx; f.ey = hy - (float)jy; f.ez = hz - (float)jz;
+    const uint32_t row = (uint32_t)sc.R * kChannels, plane = (uint32_t)sc.R * row;
+    f.prow = row;
+    f.op[0] = (uint32_t)jz * row + (uint32_t)jy * kChannels;
+    f.op[1] = plane + (uint32_t)jz * row + (uint32_t)jx * kChannels;
+    f.op[2] = 2u * plane + (uint32_t)jy * row + (uint32_t)jx * kChannels;
+    // ---- sparse 3D grid, trilinear inside one apron brick
+    const float gs = (float)sc.L * 0.25f, gmax = (float)(sc.L - 1);
+    float gx = fminf(fmaxf(fmaf(p.x + 2.0f, gs, -0.5f), 0.0f), gmax);
+    float gy = fminf(fmaxf(fmaf(p.y + 2.0f, gs, -0.5f), 0.0f), gmax);
+    float gz = fminf(fmaxf(fmaf(p.z + 2.0f, gs, -0.5f), 0.0f), gmax);
+    int ix = min((int)gx, sc.L - 2), iy = min((int)gy, sc.L - 2), iz = min((int)gz, sc.L - 2);
+    f.fx = gx - (float)ix; f.fy = gy - (float)iy; f.fz = gz - (float)iz;
+    f.bi = ((uint32_t)(iz >> 3) * sc.nbl + (uint32_t)(iy >> 3)) * sc.nbl + (uint32_t)(ix >> 3);
+    f.ol = (uint32_t)((((iz & 7) * kBrick + (iy & 7)) * kBrick + (ix & 7)) * kChannels);
+    return f;
+}
+
+// The ten 16-byte texel pairs of a sample: 6 plane pairs, 4 grid pairs.
+struct Texels {
+    u32x4 t[6], g[4];
+};
+
+// Issue every load of a sample before waiting on any: the brick index first
+// (the brick loads depend on it), then the plane pairs, which overlap its
+// round trip, then the brick pairs.  The empty asm takes all ten vectors, so
+// the compiler neither splits them into per-word loads nor sinks any behind
+// the alpha test, and places one wait before it.  Every array is present on
+// the device (a scene without a grid or without planes reads an all-zero
+// stand-in), so nothing here branches.
+__device__ __forceinline__ Texels gather(const DevScene &sc, const Footprint &f) {
+    Texels x;
+    const int brick = load_at<int>(reinterpret_cast<const uint8_t *>(sc.brick_index), f.bi * 4u);
+#pragma unroll
+    for (int pl = 0; pl < 3; ++pl) {
+        x.t[2 * pl] = load_pair(sc.planes, f.op[pl]);
+        x.t[2 * pl + 1] = load_pair(sc.planes, f.op[pl] + f.prow);
+    }
+    constexpr uint32_t sy = kBrick * kChannels, sz = kBrick * kBrick * kChannels;
+    const uint32_t ob = (uint32_t)brick * kBrickBytes + f.ol;
+    x.g[0] = load_pair(sc.bricks, ob);
+    x.g[1] = load_pair(sc.bricks, ob + sy);
+    x.g[2] = load_pair(sc.bricks, ob + sz);
+    x.g[3] = load_pair(sc.bricks, ob + sz + sy);
+    asm volatile("" : "+v"(x.t[0]), "+v"(x.t[1]), "+v"(x.t[2]), "+v"(x.t[3]), "+v"(x.t[4]), "+v"(x.t[5]),
+                 "+v"(x.g[0]), "+v"(x.g[1]), "+v"(x.g[2]), "+v"(x.g[3]));
+    return x;
 }
 
 // One evaluated sample: gather, dequantise, decode, composite.
@@ -195,76 +258,35 @@ __device__ __forceinline__ u32x4 load_pair(const uint8_t *base, uint32_t off) {
 // added to uniform base pointers, so no 64-bit address arithmetic runs per lane.
 template <bool kStats, bool kFeatF16>
 __device__ __forceinline__ void shade_sample(const DevScene &sc, float3 p, float delta, Accum &acc, Counters &cnt) {
+    const Footprint f = footprint(sc, p);
+    const Texels x = gather(sc, f);
     // texel words of the 20 texels (lo = channels 0..3, hi = 4..7) and their
-    // weights: 8 grid corners, then 4 texels of each plane.  A scene without
-    // a grid (L = 0) or without planes (R = 0) leaves those weights at zero.
+    // weights: 8 grid corners, then 4 texels of each plane.  An absent source
+    // reads zero codes, so its weights do not matter.
     uint32_t lo[20], hi[20];
     float w[20];
-#pragma unroll
-    for (int i = 0; i < 20; ++i) { lo[i] = 0u; hi[i] = 0u; w[i] = 0.0f; }
-    // ---- three planes: bilinear.  Their addresses depend on no load, so they
-    // are issued first and overlap the brick-index round trip below.
-    if (sc.R > 0) {
-        const float ps = (float)sc.R * 0.25f, pmax = (float)(sc.R - 1);
-        float hx = fminf(fmaxf(fmaf(p.x + 2.0f, ps, -0.5f), 0.0f), pmax);
-        float hy = fminf(fmaxf(fmaf(p.y + 2.0f, ps, -0.5f), 0.0f), pmax);
-        float hz = fminf(fmaxf(fmaf(p.z + 2.0f, ps, -0.5f), 0.0f), pmax);
-        int jx = min((int)hx, sc.R - 2), jy = min((int)hy, sc.R - 2), jz = min((int)hz, sc.R - 2);
-        float ex = hx - (float)jx, ey = hy - (float)jy, ez = hz - (float)jz;
-        const uint32_t row = (uint32_t)sc.R * kChannels, plane = (uint32_t)sc.R * row;
-        const uint32_t o0 = (uint32_t)jz * row + (uint32_t)jy * kChannels;              // P_x(y, z)
-        const uint32_t o1 = plane + (uint32_t)jz * row + (uint32_t)jx * kChannels;      // P_y(x, z)
-        const uint32_t o2 = 2u * plane + (uint32_t)jy * row + (uint32_t)jx * kChannels; // P_z(x, y)
-        u32x4 t[6];   // each = texels (u, v) and (u + 1, v)
-        t[0] = load_pair(sc.planes, o0);
-        t[1] = load_pair(sc.planes, o0 + row);
-        t[2] = load_pair(sc.planes, o1);
-        t[3] = load_pair(sc.planes, o1 + row);
-        t[4] = load_pair(sc.planes, o2);
-        t[5] = load_pair(sc.planes, o2 + row);
-        // (u, v) weights; u/v axes are (y, z), (x, z), (x, y)
-        const float fu[3] = {ey, ex, ex}, fv[3] = {ez, ez, ey};
+    {
+        const float fu[3] = {f.ey, f.ex, f.ex}, fv[3] = {f.ez, f.ez, f.ey};   // (u, v) = (y, z), (x, z), (x, y)
 #pragma unroll
         for (int pl = 0; pl < 3; ++pl) {
             const float au = 1.0f - fu[pl], av = 1.0f - fv[pl];
-            const u32x4 r0 = t[2 * pl], r1 = t[2 * pl + 1];
+            const u32x4 r0 = x.t[2 * pl], r1 = x.t[2 * pl + 1];
             lo[8 + 4 * pl] = r0.x; hi[8 + 4 * pl] = r0.y; w[8 + 4 * pl] = au * av;
             lo[9 + 4 * pl] = r0.z; hi[9 + 4 * pl] = r0.w; w[9 + 4 * pl] = fu[pl] * av;
             lo[10 + 4 * pl] = r1.x; hi[10 + 4 * pl] = r1.y; w[10 + 4 * pl] = au * fv[pl];
             lo[11 + 4 * pl] = r1.z; hi[11 + 4 * pl] = r1.w; w[11 + 4 * pl] = fu[pl] * fv[pl];
         }
-    }
-    // ---- sparse 3D grid: trilinear footprint inside one apron brick.  Every
-    // index entry is a valid brick (absent blocks point at an all-zero brick),
-    // so the corner loads need no branch.
-    if (sc.L > 0) {
-        const float gs = (float)sc.L * 0.25f, gmax = (float)(sc.L - 1);
-        float gx = fminf(fmaxf(fmaf(p.x + 2.0f, gs, -0.5f), 0.0f), gmax);
-        float gy = fminf(fmaxf(fmaf(p.y + 2.0f, gs, -0.5f), 0.0f), gmax);
-        float gz = fminf(fmaxf(fmaf(p.z + 2.0f, gs, -0.5f), 0.0f), gmax);
-        int ix = min((int)gx, sc.L - 2), iy = min((int)gy, sc.L - 2), iz = min((int)gz, sc.L - 2);
-        float fx = gx - (float)ix, fy = gy - (float)iy, fz = gz - (float)iz;
-        const uint32_t bi = ((uint32_t)(iz >> 3) * sc.nbl + (uint32_t)(iy >> 3)) * sc.nbl + (uint32_t)(ix >> 3);
-        const int brick = load_at<int>(reinterpret_cast<const uint8_t *>(sc.brick_index), bi * 4u);
-        const uint32_t ob = (uint32_t)brick * kBrickBytes +
-                            (uint32_t)((((iz & 7) * kBrick + (iy & 7)) * kBrick + (ix & 7)) * kChannels);
-        constexpr uint32_t sy = kBrick * kChannels, sz = kBrick * kBrick * kChannels;
-        u32x4 g[4];   // corners (x, x + 1) at (y, z), (y + 1, z), (y, z + 1), (y + 1, z + 1)
-        g[0] = load_pair(sc.bricks, ob);
-        g[1] = load_pair(sc.bricks, ob + sy);
-        g[2] = load_pair(sc.bricks, ob + sz);
-        g[3] = load_pair(sc.bricks, ob + sz + sy);
-        float ax = 1.0f - fx, ay = 1.0f - fy, az = 1.0f - fz;
-        float w00 = ay * az, w10 = fy * az, w01 = ay * fz, w11 = fy * fz;
-        const float wyz[4] = {w00, w10, w01, w11};
+        // corners (x, x + 1) at (y, z), (y + 1, z), (y, z + 1), (y + 1, z + 1)
+        const float ax = 1.0f - f.fx, ay = 1.0f - f.fy, az = 1.0f - f.fz;
+        const float wyz[4] = {ay * az, f.fy * az, ay * f.fz, f.fy * f.fz};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            lo[2 * i] = g[i].x; hi[2 * i] = g[i].y; w[2 * i] = ax * wyz[i];
-            lo[2 * i + 1] = g[i].z; hi[2 * i + 1] = g[i].w; w[2 * i + 1] = fx * wyz[i];
+            lo[2 * i] = x.g[i].x; hi[2 * i] = x.g[i].y; w[2 * i] = ax * wyz[i];
+            lo[2 * i + 1] = x.g[i].z; hi[2 * i + 1] = x.g[i].w; w[2 * i + 1] = f.fx * wyz[i];
         }
     }
     // number of sources whose weights sum to one
-    const float nsrc = (sc.L > 0 ? 1.0f : 0.0f) + (sc.R > 0 ? 3.0f : 0.0f);
+    const float nsrc = sc.nsrc;
     // ---- Eq. 8 dequantises each code affinely, q(b) = a b - m with a = 2m/255,
     // and the weights of each present source sum to one, so
     // sum_i w_i q(b_i) = a * sum_i w_i b_i - n m exactly (n sources: 4 for
@@ -499,7 +521,9 @@ __device__ __forceinline__ float3 deferred_mlp_mfma(const float *__restrict__ W,
     return make_float3(xs[lane * kXStride + 0], xs[lane * kXStride + 1], xs[lane * kXStride + 2]);
 }
 
-template <bool kStats, int kMlpPrec, bool kFeatF16>
+// kLevels: empty space is skipped with the occupancy levels themselves
+// (skip_mode 1) instead of the distance grid (skip_mode 0).
+template <bool kStats, int kMlpPrec, bool kFeatF16, bool kLevels>
 __global__ __launch_bounds__(64) void k_render(const DevScene sc, const RenderBatch rb) {
     __shared__ float xs[64 * kXStride];
     const int tile = xcd_remap((int)blockIdx.x, rb.total_tiles);
@@ -559,35 +583,69 @@ __global__ __launch_bounds__(64) void k_render(const DevScene sc, const RenderBa
             const float um = 0.5f * (u0 + u1);
             p = make_float3(fmaf(um, s.e.x, s.A.x), fmaf(um, s.e.y, s.A.y), fmaf(um, s.e.z, s.A.z));
             if (kStats) ++cnt.visited;
-            // occupancy, coarse to fine: stop at the first empty level.  A cell
-            // seen occupied stays known until the segment leaves it (its exit
-            // minus the guard), so later samples inside it need no lookup.
+            // empty >= 0: the sample is in empty space, which the segment
+            // leaves at parameter uexit.  A cell seen occupied stays known
+            // until the segment leaves it (its exit minus the guard), so later
+            // samples inside it need no lookup.
             int empty = -1;
             float uexit = 0.0f;
-#pragma unroll
-            for (int l = 0; l < kMaxLevels; ++l) {
-                if (l < sc.occ_levels && empty < 0 && !(um < known[l])) {
-                    const int rl = sc.occ_res[l];
-                    const float os = (float)rl * 0.25f;
-                    const int qx = clampi((int)floorf((p.x + 2.0f) * os), 0, rl - 1);
-                    const int qy = clampi((int)floorf((p.y + 2.0f) * os), 0, rl - 1);
-                    const int qz = clampi((int)floorf((p.z + 2.0f) * os), 0, rl - 1);
+            if constexpr (!kLevels) {
+                // distance grid: a cell at Chebyshev distance D > 0 from the
+                // nearest occupied cell is the centre of an empty cube of
+                // 2D - 1 cells; leave the whole cube (D = 0: occupied, the
+                // cube is the cell itself)
+                if (!(um < known[0])) {
+                    const int r = sc.dist_res;
+                    const float os = (float)r * 0.25f;
+                    const int qx = clampi((int)floorf((p.x + 2.0f) * os), 0, r - 1);
+                    const int qy = clampi((int)floorf((p.y + 2.0f) * os), 0, r - 1);
+                    const int qz = clampi((int)floorf((p.z + 2.0f) * os), 0, r - 1);
                     if (kStats) ++cnt.occ_lookups;
-                    const bool occ = sc.occ[l][((uint32_t)qz * rl + qy) * rl + qx] != 0;
-                    // exit parameter of this cell along the segment (slab test)
-                    const float h = sc.occ_cell[l];
-                    const float bx = (float)(s.e.x > 0.0f ? qx + 1 : qx) * h - 2.0f;
-                    const float by = (float)(s.e.y > 0.0f ? qy + 1 : qy) * h - 2.0f;
-                    const float bz = (float)(s.e.z > 0.0f ? qz + 1 : qz) * h - 2.0f;
+                    const int D = sc.dist[((uint32_t)qz * r + qy) * r + qx];
+                    const int ext = D > 0 ? D - 1 : 0;
+                    const float h = sc.dist_cell;
+                    const float bx = (float)(s.e.x > 0.0f ? qx + ext + 1 : qx - ext) * h - 2.0f;
+                    const float by = (float)(s.e.y > 0.0f ? qy + ext + 1 : qy - ext) * h - 2.0f;
+                    const float bz = (float)(s.e.z > 0.0f ? qz + ext + 1 : qz - ext) * h - 2.0f;
                     const float tx = s.e.x != 0.0f ? (bx - s.A.x) * s.iex : kInf;
                     const float ty = s.e.y != 0.0f ? (by - s.A.y) * s.iey : kInf;
                     const float tz = s.e.z != 0.0f ? (bz - s.A.z) * s.iez : kInf;
                     const float ue = fminf(tx, fminf(ty, tz));
-                    if (occ) {
-                        known[l] = ue - kSkipGuard;
+                    if (D == 0) {
+                        known[0] = ue - kSkipGuard;
                     } else {
-                        empty = l;
+                        empty = 0;
                         uexit = ue;
+                    }
+                }
+            } else {
+                // the occupancy levels, coarse to fine: stop at the first
+                // empty level and leave its cell
+#pragma unroll
+                for (int l = 0; l < kMaxLevels; ++l) {
+                    if (l < sc.occ_levels && empty < 0 && !(um < known[l])) {
+                        const int rl = sc.occ_res[l];
+                        const float os = (float)rl * 0.25f;
+                        const int qx = clampi((int)floorf((p.x + 2.0f) * os), 0, rl - 1);
+                        const int qy = clampi((int)floorf((p.y + 2.0f) * os), 0, rl - 1);
+                        const int qz = clampi((int)floorf((p.z + 2.0f) * os), 0, rl - 1);
+                        if (kStats) ++cnt.occ_lookups;
+                        const bool occ = sc.occ[l][((uint32_t)qz * rl + qy) * rl + qx] != 0;
+                        // exit parameter of this cell along the segment (slab test)
+                        const float h = sc.occ_cell[l];
+                        const float bx = (float)(s.e.x > 0.0f ? qx + 1 : qx) * h - 2.0f;
+                        const float by = (float)(s.e.y > 0.0f ? qy + 1 : qy) * h - 2.0f;
+                        const float bz = (float)(s.e.z > 0.0f ? qz + 1 : qz) * h - 2.0f;
+                        const float tx = s.e.x != 0.0f ? (bx - s.A.x) * s.iex : kInf;
+                        const float ty = s.e.y != 0.0f ? (by - s.A.y) * s.iey : kInf;
+                        const float tz = s.e.z != 0.0f ? (bz - s.A.z) * s.iez : kInf;
+                        const float ue = fminf(tx, fminf(ty, tz));
+                        if (occ) {
+                            known[l] = ue - kSkipGuard;
+                        } else {
+                            empty = l;
+                            uexit = ue;
+                        }
                     }
                 }
             }
@@ -667,15 +725,22 @@ __global__ void k_dequant(const uint8_t *__restrict__ codes, int64_t n, float m,
 
 }  // namespace
 
-template <bool kStats, bool kFeatF16>
+template <bool kStats, bool kFeatF16, bool kLevels>
 const void *render_kernel_mlp(int mlp_prec) {
-    return mlp_prec == 0 ? (const void *)k_render<kStats, 0, kFeatF16>
-         : mlp_prec == 1 ? (const void *)k_render<kStats, 1, kFeatF16> : (const void *)k_render<kStats, 2, kFeatF16>;
+    return mlp_prec == 0 ? (const void *)k_render<kStats, 0, kFeatF16, kLevels>
+         : mlp_prec == 1 ? (const void *)k_render<kStats, 1, kFeatF16, kLevels>
+                         : (const void *)k_render<kStats, 2, kFeatF16, kLevels>;
+}
+
+template <bool kStats, bool kLevels>
+const void *render_kernel_feat(const RenderBatch &rb) {
+    return rb.feat_prec ? render_kernel_mlp<kStats, true, kLevels>(rb.mlp_prec)
+                        : render_kernel_mlp<kStats, false, kLevels>(rb.mlp_prec);
 }
 
 const void *render_kernel(const RenderBatch &rb) {
-    if (rb.stats) return rb.feat_prec ? render_kernel_mlp<true, true>(rb.mlp_prec) : render_kernel_mlp<true, false>(rb.mlp_prec);
-    return rb.feat_prec ? render_kernel_mlp<false, true>(rb.mlp_prec) : render_kernel_mlp<false, false>(rb.mlp_prec);
+    if (rb.stats) return rb.skip_mode ? render_kernel_feat<true, true>(rb) : render_kernel_feat<true, false>(rb);
+    return rb.skip_mode ? render_kernel_feat<false, true>(rb) : render_kernel_feat<false, false>(rb);
 }
 
 dim3 render_grid(const RenderBatch &rb) { return dim3((unsigned)rb.total_tiles); }

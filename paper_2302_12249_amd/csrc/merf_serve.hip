@@ -42,7 +42,7 @@ struct SceneEntry {
     int active = 0;                          // queued + running requests
 };
 
-constexpr int kVariants = 6;                 // MLP fp32 / fp16 / bf16  x  features fp32 / fp16
+constexpr int kVariants = 12;                // MLP fp32 / fp16 / bf16  x  features fp32 / fp16  x  skip mode
 
 struct Slot {
     hipStream_t stream = nullptr;
@@ -87,7 +87,7 @@ bool server_live(merf_server *s) {
 // Same scene and same parameters: the requests can share one launch.
 bool same_batch_key(const Request &a, const Request &b) {
     return a.scene == b.scene && a.step == b.step && a.p.t_min == b.p.t_min && a.p.delta_mode == b.p.delta_mode &&
-           a.p.mlp_prec == b.p.mlp_prec && a.p.feat_prec == b.p.feat_prec;
+           a.p.mlp_prec == b.p.mlp_prec && a.p.feat_prec == b.p.feat_prec && a.p.skip_mode == b.p.skip_mode;
 }
 
 // Launch rb on the slot: a plain launch, or the slot's graph for this kernel
@@ -95,7 +95,7 @@ bool same_batch_key(const Request &a, const Request &b) {
 hipError_t launch_on_slot(Slot &sl, const DevScene &sc, const RenderBatch &rb, bool graphs, bool *was_graph) {
     *was_graph = false;
     if (!graphs) return launch_render(sc, rb, sl.stream);
-    const int v = rb.mlp_prec + 3 * rb.feat_prec;
+    const int v = rb.mlp_prec + 3 * rb.feat_prec + 6 * rb.skip_mode;
     void *args[] = {const_cast<DevScene *>(&sc), const_cast<RenderBatch *>(&rb)};
     hipError_t e = hipSuccess;
     if (!sl.exec[v]) {
@@ -365,7 +365,7 @@ int merf_server_submit(merf_server_t S, int32_t scene_id, const merf_camera *cam
         if (it == S->scenes.end()) return fail(MERF_E_INVALID, "unknown scene %d", scene_id);
         const DevScene *ds = scene_dev(it->second.h);
         Request r;
-        if ((rc = check_params(p, ds ? std::max(ds->R, ds->L) : 1, &r.step))) return rc;
+        if ((rc = check_params(p, ds ? ds->res : 1, &r.step))) return rc;
         r.scene = scene_id;
         r.cam = *cam;
         r.p = *p;

@@ -49,11 +49,12 @@ class merf_camera(C.Structure):
 class merf_render_params(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("step", C.c_float), ("t_min", C.c_float),
                 ("delta_mode", C.c_int32), ("mlp_prec", C.c_int32), ("feat_prec", C.c_int32),
-                ("stats_dev", C.c_void_p)]
+                ("skip_mode", C.c_int32), ("stats_dev", C.c_void_p)]
 
 
 EXPORTS = ["merf_scene_upload", "merf_render", "merf_free", "merf_last_error", "merf_set_hbm_budget",
-           "merf_hbm_in_use", "merf_scene_bytes", "merf_dequantize", "merf_occupancy_pyramid"]
+           "merf_hbm_in_use", "merf_scene_bytes", "merf_dequantize", "merf_occupancy_pyramid",
+           "merf_distance_grid"]
 
 _lib = None
 
@@ -86,6 +87,9 @@ def load(path: str = LIB_PATH):
     lib.merf_occupancy_pyramid.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_int32,
                                            C.POINTER(C.c_void_p), C.c_void_p]
     lib.merf_occupancy_pyramid.restype = C.c_int
+    lib.merf_distance_grid.argtypes = [C.POINTER(C.c_void_p), C.POINTER(C.c_int32), C.c_int32, C.c_void_p,
+                                       C.c_void_p]
+    lib.merf_distance_grid.restype = C.c_int
     _lib = lib
     return lib
 
@@ -174,13 +178,17 @@ def camera_array(cams):
     return arr
 
 
+SKIP = {"distance": 0, "levels": 1}
+
+
 def render_params(step: float = 0.0, t_min: float = 2e-4, delta_mode: int = 0, mlp_prec="f32",
-                  feat_prec="f32", stats_ptr: Optional[int] = None) -> merf_render_params:
+                  feat_prec="f32", skip="distance", stats_ptr: Optional[int] = None) -> merf_render_params:
     p = merf_render_params()
     p.struct_size = C.sizeof(merf_render_params)
     p.step, p.t_min, p.delta_mode = float(step), float(t_min), int(delta_mode)
     p.mlp_prec = PREC[mlp_prec] if isinstance(mlp_prec, str) else int(mlp_prec)
     p.feat_prec = PREC[feat_prec] if isinstance(feat_prec, str) else int(feat_prec)
+    p.skip_mode = SKIP[skip] if isinstance(skip, str) else int(skip)
     p.stats_dev = stats_ptr
     return p
 
@@ -209,6 +217,22 @@ def occupancy_pyramid(mask, factors, stream=None):
     _check(load().merf_occupancy_pyramid(C.c_void_p(mask.data_ptr()), r, fac, len(factors), ptrs,
                                          C.c_void_p(st.cuda_stream)))
     return outs
+
+
+def distance_grid(levels, stream=None):
+    """Empty-space distance grid of an occupancy hierarchy (merf_distance_grid).
+    levels: torch uint8 cubes [r_l, r_l, r_l] on the GPU, coarse to fine; returns
+    a torch uint8 [r, r, r] for the finest r."""
+    import torch
+    for o in levels:
+        assert o.is_cuda and o.dtype == torch.uint8 and o.is_contiguous() and o.dim() == 3
+    r = int(levels[-1].shape[0])
+    out = torch.empty((r, r, r), dtype=torch.uint8, device=levels[-1].device)
+    ptrs = (C.c_void_p * len(levels))(*[o.data_ptr() for o in levels])
+    res = (C.c_int32 * len(levels))(*[int(o.shape[0]) for o in levels])
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(load().merf_distance_grid(ptrs, res, len(levels), C.c_void_p(out.data_ptr()), C.c_void_p(st.cuda_stream)))
+    return out
 
 
 class Renderer:

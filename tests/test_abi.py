@@ -100,6 +100,7 @@ def _upload_rc(mutate):
     ("m_density", lambda d, k: setattr(d, "m_density", 0.0)),
     ("planes", lambda d, k: setattr(d, "planes", None)),
     ("num_blocks", lambda d, k: setattr(d, "num_blocks", 1)),
+    ("occ_nesting", lambda d, k: d.occ_res.__setitem__(0, 6)),    # 16 is not a multiple of 6
 ])
 def test_upload_rejects_bad_descriptors(name, mutate):
     rc, msg, h = _upload_rc(mutate)
@@ -160,6 +161,18 @@ def test_occupancy_pyramid_argument_checks():
     assert lib.merf_occupancy_pyramid(C.c_void_p(16), 16, fac, 2, ptrs, None) == merf.MERF_E_INVALID  # 3 does not divide 16
     assert lib.merf_occupancy_pyramid(C.c_void_p(16), 0, fac, 1, ptrs, None) == merf.MERF_E_INVALID
     assert lib.merf_occupancy_pyramid(None, 16, fac, 1, ptrs, None) == merf.MERF_E_INVALID
+
+
+def test_distance_grid_argument_checks():
+    lib = merf.load()
+    ptrs = (C.c_void_p * 2)(16, 16)
+    res = (C.c_int32 * 2)(6, 16)                # 16 is not a multiple of 6
+    assert lib.merf_distance_grid(ptrs, res, 2, C.c_void_p(16), None) == merf.MERF_E_INVALID
+    res = (C.c_int32 * 2)(8, 2048)              # finest resolution above 1024
+    assert lib.merf_distance_grid(ptrs, res, 2, C.c_void_p(16), None) == merf.MERF_E_INVALID
+    res = (C.c_int32 * 2)(8, 16)
+    assert lib.merf_distance_grid(ptrs, res, 0, C.c_void_p(16), None) == merf.MERF_E_INVALID
+    assert lib.merf_distance_grid(ptrs, res, 2, None, None) == merf.MERF_E_INVALID
 
 
 def test_representation_variants_validate():

@@ -54,3 +54,47 @@ def test_device_pyramid_renders_like_host_pyramid(torch, merf, tiny_scene, tiny_
     ref, st = oracle.render(tiny_scene, tiny_cams)
     ok = st["fragile"] == 0
     assert np.abs(gpu - ref)[ok].max() <= 2.0 / 255.0
+
+
+def chebyshev_brute(levels):
+    """Distance grid by definition: for each finest cell, the L-infinity
+    distance in cells to the nearest cell occupied at every level (capped at
+    255; 255 when there is none)."""
+    rf = levels[-1].shape[0]
+    comb = np.ones((rf,) * 3, bool)
+    for o in levels:
+        k = rf // o.shape[0]
+        comb &= np.repeat(np.repeat(np.repeat(o > 0, k, 0), k, 1), k, 2)
+    occ = np.argwhere(comb).astype(np.int32)
+    if len(occ) == 0:
+        return np.full((rf,) * 3, 255, np.uint8)
+    cells = np.indices((rf,) * 3).reshape(3, -1).T.astype(np.int32)
+    best = np.full(len(cells), 255, np.int32)
+    for i in range(0, len(occ), 64):
+        d = np.abs(cells[:, None, :] - occ[None, i:i + 64, :]).max(axis=2).min(axis=1)
+        best = np.minimum(best, d)
+    return np.minimum(best, 255).astype(np.uint8).reshape((rf,) * 3)
+
+
+@pytest.mark.parametrize("case", ["pyramid", "and_of_levels", "empty", "cap"])
+def test_distance_grid_matches_definition(torch, merf, case):
+    print(f"distance grid: {case}", flush=True)
+    rng = np.random.default_rng(7)
+    if case == "pyramid":            # a max-pool pyramid 4 / 16 / 32
+        fine = (rng.random((32, 32, 32)) < 0.003).astype(np.uint8)
+        levels = [synth.maxpool(fine, 8), synth.maxpool(fine, 2), fine]
+    elif case == "and_of_levels":    # coarse levels that are not max-pools: the AND decides
+        fine = (rng.random((24, 24, 24)) < 0.02).astype(np.uint8)
+        levels = [(rng.random((6, 6, 6)) < 0.5).astype(np.uint8), (rng.random((12, 12, 12)) < 0.7).astype(np.uint8),
+                  fine]
+    elif case == "empty":
+        levels = [np.zeros((4, 4, 4), np.uint8), np.zeros((16, 16, 16), np.uint8)]
+    else:                            # distances beyond 255 are capped
+        fine = np.zeros((320, 320, 320), np.uint8)
+        fine[3, 5, 7] = 1
+        levels = [fine]
+    want = chebyshev_brute(levels)
+    got = merf.distance_grid([torch.from_numpy(np.ascontiguousarray(o)).cuda() for o in levels])
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    assert np.array_equal(got, want), np.argwhere(got != want)[:5]

@@ -126,6 +126,18 @@ def test_stats_counters_match_oracle(torch, merf, tiny_scene, tiny_cams):
     assert 0 < lookups <= visited * len(tiny_scene.occ)
 
 
+@pytest.mark.parametrize("kw", [{}, {"t_min": 0.0, "step": 1.0 / 32}, {"delta_mode": 1}])
+def test_skip_modes_render_the_same_image(torch, merf, tiny_scene, tiny_cams, kw):
+    say(f"tiny: distance-grid skipping vs level-by-level skipping {kw}")
+    a, ca = gpu_render(torch, merf, tiny_scene, tiny_cams, stats=True, skip="distance", **kw)
+    b, cb = gpu_render(torch, merf, tiny_scene, tiny_cams, stats=True, skip="levels", **kw)
+    say(f"  visited {ca[2]} vs {cb[2]}, lookups {ca[1]} vs {cb[1]}, evaluated {ca[3]} vs {cb[3]}")
+    # both skip only samples in empty cells, so they evaluate the same samples
+    assert np.array_equal(a, b)
+    assert ca[3] == cb[3] and ca[4] == cb[4] and ca[5] == cb[5]
+    assert ca[2] <= cb[2]
+
+
 def test_ragged_batch_and_offsets(torch, merf, tiny_scene):
     say("ragged multi-camera batch")
     base = synth.tiny_camera()
@@ -220,6 +232,9 @@ def test_full_1080p_parity_sampled_rows(torch, merf, full_scene):
     sel = (rows[:, None] * W + np.arange(W)[None, :]).reshape(-1)
     check(gpu[sel], ref, st["fragile"], "full 1080p sampled rows")
     assert gpu[:, 3].max() > 0.5      # the view sees content
+    # the paper's level-by-level skipping gives the same image
+    lv = gpu_render(torch, merf, full_scene, cams, skip="levels")
+    assert np.array_equal(gpu, lv)
 
 
 def test_full_scene_orbit_views_sampled(torch, merf, full_scene):
