@@ -16,6 +16,9 @@ ARCH = "gfx950"
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Wall", "-Wno-unused-function",
+    # mul + add are fused only within one expression (fmaf where wanted), so
+    # every kernel instance rounds the steps they share in the same way
+    "-ffp-contract=on",
     # packed fp32 instructions are kept out of the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-fno-gpu-rdc",

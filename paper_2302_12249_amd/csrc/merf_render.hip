@@ -25,6 +25,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "merf_device.h"
 
 namespace merf {
@@ -413,11 +415,22 @@ __device__ __forceinline__ void open_segment(float3 o, float3 d, float ta, int r
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef _Float16 halfx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-// LDS row of one pixel: the 34 inputs zero-padded to 48 (three K = 16 steps
-// of the half-precision products read up to index 47); odd stride, so the 16
-// rows read by one instruction fall in different banks.
-constexpr int kXWidth = 48;
-constexpr int kXStride = kXWidth + 1;
+// LDS staging of the inputs, one row per pixel, sized so that four waves fit
+// per SIMD (16 workgroups of one wave in a CU's 160 KB):
+//   fp32: 36 floats (the 34 inputs zero-padded to nine K = 4 steps), row
+//         stride 37 floats -- odd, so the 16 rows one instruction reads fall in
+//         different banks;
+//   fp16 / bf16: the inputs already converted, 48 halves (three K = 16
+//         steps), row stride 52 halves = 26 banks, so the 16 eight-byte reads
+//         of one instruction cover the 32 banks once.
+// The outputs reuse the buffer as floats with the row stride kOut.
+template <int kPrec>
+struct MlpLds {
+    static constexpr int kWidth = kPrec == 0 ? 36 : 48;      // inputs per row
+    static constexpr int kStride = kPrec == 0 ? 37 : 52;     // elements per row
+    static constexpr int kOut = kPrec == 0 ? 37 : 26;        // floats per row of the outputs
+    static constexpr int kFloats = 64 * (kPrec == 0 ? 37 : 26);
+};
 
 __device__ __forceinline__ void mlp_encode(float *x, const Accum &acc, float3 d) {
     x[0] = acc.cd0; x[1] = acc.cd1; x[2] = acc.cd2;
@@ -430,36 +443,49 @@ __device__ __forceinline__ void mlp_encode(float *x, const Accum &acc, float3 d)
         x[22 + 3 * k] = __cosf(d.x * sc); x[23 + 3 * k] = __cosf(d.y * sc); x[24 + 3 * k] = __cosf(d.z * sc);
     }
 #pragma unroll
-    for (int k = kMlpIn; k < kXWidth; ++k) x[k] = 0.0f;
+    for (int k = kMlpIn; k < 48; ++k) x[k] = 0.0f;
+}
+
+// Half-precision operand type of kPrec 1 (fp16) and 2 (bf16).
+template <int kPrec>
+using half4_t = typename std::conditional<kPrec == 1, halfx4, bf16x4>::type;
+template <int kPrec>
+using half_t = typename std::conditional<kPrec == 1, _Float16, __bf16>::type;
+
+template <int kPrec>
+__device__ __forceinline__ half4_t<kPrec> to_half4(const float v[4]) {
+    using H = half_t<kPrec>;
+    return half4_t<kPrec>{(H)v[0], (H)v[1], (H)v[2], (H)v[3]};
 }
 
 // 16x16 block product with K = 16 in half precision: lane l supplies
 // A[l % 16][4(l/16) .. +3] and B[4(l/16) .. +3][l % 16].
 template <int kPrec>
-__device__ __forceinline__ floatx4 mfma16(const float a[4], const float b[4], floatx4 c) {
-    if constexpr (kPrec == 1) {
-        halfx4 ha = {(_Float16)a[0], (_Float16)a[1], (_Float16)a[2], (_Float16)a[3]};
-        halfx4 hb = {(_Float16)b[0], (_Float16)b[1], (_Float16)b[2], (_Float16)b[3]};
-        return __builtin_amdgcn_mfma_f32_16x16x16f16(ha, hb, c, 0, 0, 0);
-    } else {
-        bf16x4 ha = {(__bf16)a[0], (__bf16)a[1], (__bf16)a[2], (__bf16)a[3]};
-        bf16x4 hb = {(__bf16)b[0], (__bf16)b[1], (__bf16)b[2], (__bf16)b[3]};
-        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ha, hb, c, 0, 0, 0);
-    }
+__device__ __forceinline__ floatx4 mfma16(half4_t<kPrec> a, half4_t<kPrec> b, floatx4 c) {
+    if constexpr (kPrec == 1) return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+    else return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
 // Returns h(x) for this lane's pixel.  All 64 lanes must call it.
 template <int kPrec>
 __device__ __forceinline__ float3 deferred_mlp_mfma(const float *__restrict__ W, float *xs, const Accum &acc,
                                                     float3 d) {
+    using Lds = MlpLds<kPrec>;
     const int lane = (int)threadIdx.x, j = lane & 15, g = lane >> 4;
     const float *W0 = W, *b0 = W0 + kMlpIn * kMlpHidden, *W1 = b0 + kMlpHidden, *b1 = W1 + kMlpHidden * kMlpHidden,
                 *W2 = b1 + kMlpHidden, *b2 = W2 + kMlpHidden * kMlpOut;
     {
-        float x[kXWidth];
+        float x[48];
         mlp_encode(x, acc, d);
+        if constexpr (kPrec == 0) {
 #pragma unroll
-        for (int i = 0; i < kXWidth; ++i) xs[lane * kXStride + i] = x[i];
+            for (int i = 0; i < Lds::kWidth; ++i) xs[lane * Lds::kStride + i] = x[i];
+        } else {
+            half4_t<kPrec> *row = reinterpret_cast<half4_t<kPrec> *>(reinterpret_cast<half_t<kPrec> *>(xs) +
+                                                                    lane * Lds::kStride);
+#pragma unroll
+            for (int i = 0; i < Lds::kWidth / 4; ++i) row[i] = to_half4<kPrec>(x + 4 * i);
+        }
     }
     // layer-1 A operand W0^T[hidden j][k]: fp32 steps take k = 9g + q,
     // half-precision steps k = 16 (q / 4) + 4g + q % 4 (zero past 34)
@@ -480,14 +506,17 @@ __device__ __forceinline__ float3 deferred_mlp_mfma(const float *__restrict__ W,
     // one block of 16 pixels at a time through all three layers
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
-        const float *xr = xs + (16 * mt + j) * kXStride;
         floatx4 c = {0.0f, 0.0f, 0.0f, 0.0f};
         if constexpr (kPrec == 0) {
+            const float *xr = xs + (16 * mt + j) * Lds::kStride;
 #pragma unroll
             for (int q = 0; q < 9; ++q) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[q], xr[9 * g + q], c, 0, 0, 0);
         } else {
+            const half_t<kPrec> *xr = reinterpret_cast<const half_t<kPrec> *>(xs) + (16 * mt + j) * Lds::kStride;
 #pragma unroll
-            for (int ks = 0; ks < 3; ++ks) c = mfma16<kPrec>(a0 + 4 * ks, xr + 16 * ks + 4 * g, c);
+            for (int ks = 0; ks < 3; ++ks)
+                c = mfma16<kPrec>(to_half4<kPrec>(a0 + 4 * ks),
+                                  *reinterpret_cast<const half4_t<kPrec> *>(xr + 16 * ks + 4 * g), c);
         }
         float h[4];
 #pragma unroll
@@ -497,7 +526,7 @@ __device__ __forceinline__ float3 deferred_mlp_mfma(const float *__restrict__ W,
 #pragma unroll
             for (int q = 0; q < 4; ++q) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[q], h[q], c, 0, 0, 0);
         } else {
-            c = mfma16<kPrec>(a1, h, c);
+            c = mfma16<kPrec>(to_half4<kPrec>(a1), to_half4<kPrec>(h), c);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) h[r] = fmaxf(c[r] + b1[4 * g + r], 0.0f);
@@ -506,7 +535,7 @@ __device__ __forceinline__ float3 deferred_mlp_mfma(const float *__restrict__ W,
 #pragma unroll
             for (int q = 0; q < 4; ++q) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[q], h[q], c, 0, 0, 0);
         } else {
-            c = mfma16<kPrec>(a2, h, c);
+            c = mfma16<kPrec>(to_half4<kPrec>(a2), to_half4<kPrec>(h), c);
         }
         y[mt] = c;
     }
@@ -515,17 +544,17 @@ __device__ __forceinline__ float3 deferred_mlp_mfma(const float *__restrict__ W,
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-            for (int r = 0; r < kMlpOut; ++r) xs[(16 * mt + j) * kXStride + r] = y[mt][r] + b2[r];
+            for (int r = 0; r < kMlpOut; ++r) xs[(16 * mt + j) * Lds::kOut + r] = y[mt][r] + b2[r];
     }
     __syncthreads();
-    return make_float3(xs[lane * kXStride + 0], xs[lane * kXStride + 1], xs[lane * kXStride + 2]);
+    return make_float3(xs[lane * Lds::kOut + 0], xs[lane * Lds::kOut + 1], xs[lane * Lds::kOut + 2]);
 }
 
 // kLevels: empty space is skipped with the occupancy levels themselves
 // (skip_mode 1) instead of the distance grid (skip_mode 0).
 template <bool kStats, int kMlpPrec, bool kFeatF16, bool kLevels>
-__global__ __launch_bounds__(64) void k_render(const DevScene sc, const RenderBatch rb) {
-    __shared__ float xs[64 * kXStride];
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_render(const DevScene sc, const RenderBatch rb) {
+    __shared__ float xs[MlpLds<kMlpPrec>::kFloats];
     const int tile = xcd_remap((int)blockIdx.x, rb.total_tiles);
     int c = 0;
 #pragma unroll
