@@ -397,6 +397,48 @@ def main():
                     "visited": visited / n_rays, "occ_lookups": occ_lookups / n_rays},
         "alg_bytes_per_launch": alg_bytes,
     }
+    # the paper's level-by-level skipping (skip_mode 1) on the same frame:
+    # same image, more march steps
+    lv_img = torch.empty_like(out)
+    st_lv = torch.zeros(8, dtype=torch.int64, device="cuda")
+    r.render(cams, out=lv_img, stats=st_lv, skip="levels")
+    for _ in range(3):
+        r.render(cams, out=lv_img, skip="levels")
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(20):
+        r.render(cams, out=lv_img, skip="levels")
+    e1.record(stream)
+    torch.cuda.synchronize()
+    lv_ms = e0.elapsed_time(e1) / 20
+    c_lv = st_lv.cpu().numpy()
+    res["skip_levels"] = {"kernel_ms": lv_ms, "Mrays/s": rays / (lv_ms * 1e-3) / 1e6,
+                          "visited_per_ray": float(c_lv[2]) / n_rays, "occ_lookups_per_ray": float(c_lv[1]) / n_rays,
+                          "same_image": bool(torch.equal(lv_img, out))}
+    del lv_img
+    # gather bound: replay the frame's recorded texel loads with no arithmetic
+    rec = merf.GatherRecord(r.handle, cams, cap=96)
+    torch.cuda.synchronize()
+    counts = rec.count.cpu().numpy()
+    for _ in range(3):
+        rec.replay()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(20):
+        rec.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    rp_ms = e0.elapsed_time(e1) / 20
+    gather_bytes = evaluated * B_EVAL + contributing * B_CONTRIB + n_rays * B_RAY
+    res["gather_replay"] = {"kernel_ms": rp_ms, "gather_bytes": gather_bytes,
+                            "replay_GB/s": gather_bytes / (rp_ms * 1e-3) / 1e9,
+                            "render_GB/s": gather_bytes / (kernel_ms * 1e-3) / 1e9,
+                            "render_frac_of_replay": rp_ms / kernel_ms,
+                            "max_samples_per_ray": int(counts.max()),
+                            "unrecorded_samples": int(np.maximum(counts - rec.cap, 0).sum()),
+                            "same_image": bool(torch.equal(rec.image, out))}
+    del rec
     # precision variants of the deferred MLP (fp16 / bf16 inputs on MFMA,
     # fp32 accumulation); compositing and transmittance stay fp32
     prec = {}

@@ -1,0 +1,64 @@
+/*
+ * merf_measure.h -- measurement entry points of the MERF renderer (MI355X,
+ * gfx950): the achievable-gather bound of a view.
+ *
+ * The renderer's memory traffic is its texel gathers (Sec. 6: per evaluated
+ * sample, 8 grid voxels and 3 x 4 plane texels of 8 uint8 channels).  To
+ * bound what those gathers alone can reach, merf_record_gathers renders a
+ * view while recording, for every evaluated sample, the texel offsets it
+ * reads; merf_replay_gathers then re-issues exactly those loads, in the same
+ * order, tile layout and wave shape, with no other arithmetic.  The ratio of
+ * replay time to render time is the fraction of the gather bound the renderer
+ * reaches.
+ *
+ * Same error conventions as merf.h (0 = MERF_OK, negative codes,
+ * merf_last_error()).
+ */
+#ifndef MERF_MEASURE_H
+#define MERF_MEASURE_H
+
+#include "merf.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Number of recording slots (one per lane: 64 per 8x8 pixel tile) of a
+ * launch of n_cams cameras (host array).  Errors: MERF_E_INVALID for a bad
+ * camera or more cameras than one launch carries (16). */
+int merf_gather_slots(const merf_camera *cams, int32_t n_cams, int32_t *n_slots);
+
+/*
+ * Render cams (at most 16, one launch) exactly as merf_render does, into
+ * out_rgba_dev, and record the gathers.  p->stats_dev must be set (the
+ * recording runs in the counting variant of the kernel, which also adds its
+ * counters there).  count_dev: device int32[n_slots] receives the number of
+ * evaluated samples of each slot.  rec_dev: device uint32[cap][n_slots][4]
+ * receives, for evaluated sample k < cap of slot q, at [k][q]: the byte
+ * offsets of the (u, v) texels of the three planes and (brick index entry
+ * << 13 | byte offset in the brick) of the grid footprint.  Samples k >= cap
+ * are counted but not recorded.  Requires (grid_res / 8)^3 <= 2^19 so that
+ * the grid word packs.  Asynchronous on hip_stream.
+ * Errors: MERF_E_INVALID for a bad handle, camera, parameter, cap < 1, NULL
+ * buffers or a grid too large to pack; MERF_E_DEVICE if the launch fails.
+ */
+int merf_record_gathers(merf_scene_t s, const merf_camera *cams, int32_t n_cams, const merf_render_params *p,
+                        uint32_t *rec_dev, int32_t cap, int32_t *count_dev, float *out_rgba_dev, void *hip_stream);
+
+/*
+ * Re-issue the recorded loads of n_slots slots (rec_dev, count_dev and cap as
+ * given to merf_record_gathers for scene s) and write one float4 per slot to
+ * out_dev (device, n_slots * 4 floats): its recorded sample count, then
+ * values with no meaning that keep the loads live.  Asynchronous on
+ * hip_stream.
+ * Errors: MERF_E_INVALID for a bad handle, n_slots not a positive multiple of
+ * 64, cap < 1 or NULL buffers; MERF_E_DEVICE if the launch fails.
+ */
+int merf_replay_gathers(merf_scene_t s, const uint32_t *rec_dev, const int32_t *count_dev, int32_t cap,
+                        int32_t n_slots, float *out_dev, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MERF_MEASURE_H */

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmerf_hip.so")
-SOURCES = ["merf_api.hip", "merf_render.hip", "merf_serve.hip", "merf_ingest.hip"]
+SOURCES = ["merf_api.hip", "merf_render.hip", "merf_serve.hip", "merf_ingest.hip", "merf_measure.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -70,6 +70,12 @@ struct RenderBatch {
     float step, inv_step, t_min;
     int32_t delta_mode, mlp_prec, feat_prec, skip_mode;
     unsigned long long *stats;
+    // gather record (statistics variant only; null = off): evaluated sample
+    // k of launch slot q = 64 tile + lane writes its texel offsets to
+    // rec[k * 64 total_tiles + q] when k < rec_cap; rec_count[q] = samples
+    uint32_t *rec;
+    int32_t *rec_count;
+    int32_t rec_cap;
     DevCamera cams[kCamsPerLaunch];
 };
 
@@ -79,6 +85,10 @@ hipError_t launch_render(const DevScene &sc, const RenderBatch &rb, hipStream_t 
 const void *render_kernel(const RenderBatch &rb);
 dim3 render_grid(const RenderBatch &rb);
 constexpr int kRenderBlock = 64;
+// Gather replay (measurement): re-issues the recorded texel loads of a
+// launch of total_tiles tiles with no arithmetic; out: float4 per slot.
+hipError_t launch_gather_replay(const DevScene &sc, const uint32_t *rec, const int32_t *rec_count, int cap,
+                                int total_tiles, float *out, hipStream_t stream);
 hipError_t launch_dequant(const uint8_t *codes, int64_t n, float m, int prec, void *out, hipStream_t stream);
 // merf_ingest.hip: brick_pos[i] = bx | by << 10 | bz << 20 of brick slot i.
 hipError_t launch_pack_bricks(const uint8_t *blocks, const int32_t *block_index, const int32_t *brick_pos,

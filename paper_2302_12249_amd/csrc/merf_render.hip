@@ -710,6 +710,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
             s.k = max(s.k + 1, knext);
         }
         if (found) {
+            if (kStats && rb.rec) {
+                // measurement: record the texel offsets of this sample
+                const uint32_t k = cnt.evaluated;
+                if (k < (uint32_t)rb.rec_cap) {
+                    const Footprint f = footprint(sc, p);
+                    const uint32_t q = (uint32_t)tile * 64u + (uint32_t)lane;
+                    *reinterpret_cast<u32x4 *>(rb.rec + 4 * ((size_t)k * (size_t)rb.total_tiles * 64u + q)) =
+                        u32x4{f.op[0], f.op[1], f.op[2], (f.bi << 13) | f.ol};
+                }
+            }
             shade_sample<kStats, kFeatF16>(sc, p, delta, acc, cnt);
             ++s.k;
             if (acc.T < rb.t_min) {          // early termination (Sec. 6)
@@ -724,6 +734,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
         float4 rgba = make_float4(acc.cd0 + h.x, acc.cd1 + h.y, acc.cd2 + h.z, 1.0f - acc.T);
         *reinterpret_cast<float4 *>(cam.out + ((int64_t)py * cam.width + px) * 4) = rgba;
     }
+    if (kStats && rb.rec_count) rb.rec_count[tile * 64 + lane] = (int32_t)cnt.evaluated;
     if (kStats) {
         unsigned long long v[6] = {active ? 1ull : 0ull, cnt.occ_lookups, cnt.visited, cnt.evaluated, cnt.contributing,
                                    terminated ? 1ull : 0ull};
@@ -735,6 +746,45 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
             if (lane == 0 && x) atomicAdd(rb.stats + i, x);
         }
     }
+}
+
+// Gather replay (measurement only): each lane re-issues, round by round, the
+// texel loads the renderer made for its pixel -- the brick slot, then the six
+// plane pairs and the four brick pairs -- with the same tile order and wave
+// shape, and no arithmetic beyond the addresses.  Its time bounds what the
+// renderer's gathers alone can reach on this working set.
+__global__ __launch_bounds__(64) void k_gather_replay(const DevScene sc, const uint32_t *__restrict__ rec,
+                                                      const int32_t *__restrict__ rec_count, int cap,
+                                                      int total_tiles, float *__restrict__ out) {
+    const int tile = xcd_remap((int)blockIdx.x, total_tiles);
+    const uint32_t q = (uint32_t)tile * 64u + threadIdx.x;
+    const size_t slots = (size_t)total_tiles * 64u;
+    const int n = min(rec_count[q], cap);
+    const uint32_t prow = (uint32_t)sc.R * kChannels;
+    uint32_t sink = 0u;
+    for (int k = 0; __any(k < n); ++k) {
+        if (k < n) {
+            const u32x4 r = *reinterpret_cast<const u32x4 *>(rec + 4 * ((size_t)k * slots + q));
+            const int brick = load_at<int>(reinterpret_cast<const uint8_t *>(sc.brick_index), (r.w >> 13) * 4u);
+            Texels x;
+#pragma unroll
+            for (int pl = 0; pl < 3; ++pl) {
+                const uint32_t o = pl == 0 ? r.x : (pl == 1 ? r.y : r.z);
+                x.t[2 * pl] = load_pair(sc.planes, o);
+                x.t[2 * pl + 1] = load_pair(sc.planes, o + prow);
+            }
+            constexpr uint32_t sy = kBrick * kChannels, sz = kBrick * kBrick * kChannels;
+            const uint32_t ob = (uint32_t)brick * kBrickBytes + (r.w & 8191u);
+            x.g[0] = load_pair(sc.bricks, ob);
+            x.g[1] = load_pair(sc.bricks, ob + sy);
+            x.g[2] = load_pair(sc.bricks, ob + sz);
+            x.g[3] = load_pair(sc.bricks, ob + sz + sy);
+            asm volatile("" : "+v"(x.t[0]), "+v"(x.t[1]), "+v"(x.t[2]), "+v"(x.t[3]), "+v"(x.t[4]), "+v"(x.t[5]),
+                         "+v"(x.g[0]), "+v"(x.g[1]), "+v"(x.g[2]), "+v"(x.g[3]));
+            sink ^= x.t[0].x ^ x.g[0].x;
+        }
+    }
+    reinterpret_cast<float4 *>(out)[q] = make_float4((float)n, (float)(sink & 1u), 0.0f, 0.0f);
 }
 
 // Eq. 8 dequantisation, correctly rounded to the output format.  Rounding the
@@ -778,6 +828,14 @@ hipError_t launch_render(const DevScene &sc, const RenderBatch &rb, hipStream_t 
     if (rb.total_tiles <= 0) return hipSuccess;
     void *args[] = {const_cast<DevScene *>(&sc), const_cast<RenderBatch *>(&rb)};
     return hipLaunchKernel(render_kernel(rb), render_grid(rb), dim3(kRenderBlock), args, 0, stream);
+}
+
+hipError_t launch_gather_replay(const DevScene &sc, const uint32_t *rec, const int32_t *rec_count, int cap,
+                                int total_tiles, float *out, hipStream_t stream) {
+    if (total_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_replay, dim3((unsigned)total_tiles), dim3(64), 0, stream, sc, rec, rec_count, cap,
+                       total_tiles, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_dequant(const uint8_t *codes, int64_t n, float m, int prec, void *out, hipStream_t stream) {

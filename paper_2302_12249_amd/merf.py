@@ -308,6 +308,56 @@ def _serve_lib():
     return lib
 
 
+MEASURE_EXPORTS = ["merf_gather_slots", "merf_record_gathers", "merf_replay_gathers"]
+
+
+def _measure_lib():
+    lib = load()
+    if getattr(lib, "_measure_ready", False):
+        return lib
+    vp, i32 = C.c_void_p, C.c_int32
+    lib.merf_gather_slots.argtypes = [C.POINTER(merf_camera), i32, C.POINTER(i32)]
+    lib.merf_record_gathers.argtypes = [vp, C.POINTER(merf_camera), i32, C.POINTER(merf_render_params), vp, i32, vp,
+                                        vp, vp]
+    lib.merf_replay_gathers.argtypes = [vp, vp, vp, i32, i32, vp, vp]
+    for n in MEASURE_EXPORTS:
+        getattr(lib, n).restype = C.c_int
+    lib._measure_ready = True
+    return lib
+
+
+class GatherRecord:
+    """Record the texel gathers of one launch (merf_record_gathers) and replay
+    them without arithmetic (merf_replay_gathers).  Buffers are torch tensors."""
+
+    def __init__(self, handle: int, cams, cap: int = 64, **params):
+        import torch
+        lib = _measure_lib()
+        self.handle, self.cap = handle, int(cap)
+        arr = camera_array(cams)
+        n = C.c_int32()
+        _check(lib.merf_gather_slots(arr, len(cams), C.byref(n)))
+        self.n_slots = n.value
+        self.rec = torch.empty((self.cap, self.n_slots, 4), dtype=torch.int32, device="cuda")
+        self.count = torch.empty(self.n_slots, dtype=torch.int32, device="cuda")
+        self.stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+        self.image = torch.empty((cams.num_pixels(), 4), dtype=torch.float32, device="cuda")
+        self.out = torch.empty((self.n_slots, 4), dtype=torch.float32, device="cuda")
+        p = render_params(stats_ptr=self.stats.data_ptr(), **params)
+        st = torch.cuda.current_stream().cuda_stream
+        _check(lib.merf_record_gathers(C.c_void_p(handle), arr, len(cams), C.byref(p), C.c_void_p(self.rec.data_ptr()),
+                                       self.cap, C.c_void_p(self.count.data_ptr()), C.c_void_p(self.image.data_ptr()),
+                                       C.c_void_p(st)))
+
+    def replay(self, stream=None):
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream()
+        _check(_measure_lib().merf_replay_gathers(C.c_void_p(self.handle), C.c_void_p(self.rec.data_ptr()),
+                                                   C.c_void_p(self.count.data_ptr()), self.cap, self.n_slots,
+                                                   C.c_void_p(self.out.data_ptr()), C.c_void_p(st.cuda_stream)))
+        return self.out
+
+
 def server_config(slots=4, max_batch=16, use_graphs=True, evict_idle=False, hbm_budget=0) -> merf_server_config:
     c = merf_server_config()
     c.struct_size = C.sizeof(merf_server_config)

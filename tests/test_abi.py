@@ -13,6 +13,7 @@ from paper_2302_12249_amd import merf
 
 HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "merf.h")
 SERVE_HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "merf_serve.h")
+MEASURE_HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "merf_measure.h")
 
 
 def declared_functions(path=HEADER):
@@ -27,12 +28,31 @@ def test_header_declares_the_binding_exports():
 
 def test_library_exports_every_declared_symbol():
     lib = merf.load()
-    for name in declared_functions() + declared_functions(SERVE_HEADER):
+    for name in declared_functions() + declared_functions(SERVE_HEADER) + declared_functions(MEASURE_HEADER):
         assert hasattr(lib, name), name
 
 
 def test_serve_header_declares_the_binding_exports():
     assert declared_functions(SERVE_HEADER) == sorted(merf.SERVE_EXPORTS)
+
+
+def test_measure_header_declares_the_binding_exports():
+    assert declared_functions(MEASURE_HEADER) == sorted(merf.MEASURE_EXPORTS)
+
+
+def test_gather_slots_and_measure_argument_checks():
+    lib = merf._measure_lib()
+    cams = synth.tiny_camera(w=20, h=9)            # 3 x 2 tiles
+    n = C.c_int32()
+    assert lib.merf_gather_slots(merf.camera_array(cams), 1, C.byref(n)) == merf.MERF_OK
+    assert n.value == 6 * 64
+    assert lib.merf_gather_slots(merf.camera_array(cams), 0, C.byref(n)) == merf.MERF_E_INVALID
+    p = merf.render_params(stats_ptr=16)
+    bogus = C.c_void_p(0x1234)
+    assert lib.merf_record_gathers(bogus, merf.camera_array(cams), 1, C.byref(p), C.c_void_p(16), 8,
+                                   C.c_void_p(16), C.c_void_p(16), None) == merf.MERF_E_INVALID
+    assert lib.merf_replay_gathers(bogus, C.c_void_p(16), C.c_void_p(16), 8, 64, C.c_void_p(16),
+                                   None) == merf.MERF_E_INVALID
 
 
 @pytest.mark.parametrize("field,value", [("slots", 0), ("slots", 9), ("max_batch", 0), ("max_batch", 17),

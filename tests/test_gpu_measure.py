@@ -1,0 +1,54 @@
+"""GPU tests of the gather record / replay measurement (include/merf_measure.h):
+recording renders the same image as merf_render, records one entry per
+evaluated sample with in-range offsets, and the replay re-issues them."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def merf():
+    from paper_2302_12249_amd import merf as m
+    m.load()
+    return m
+
+
+@pytest.mark.parametrize("cap", [64, 2])
+def test_record_and_replay(torch, merf, tiny_scene, cap):
+    print(f"gather record / replay, tiny view, cap {cap}", flush=True)
+    cams = synth.tiny_camera(w=100, h=60)          # ragged: 13 x 8 tiles
+    r = merf.Renderer(tiny_scene)
+    try:
+        plain = r.render(cams)
+        st = torch.zeros(8, dtype=torch.int64, device="cuda")
+        r.render(cams, stats=st)
+        rec = merf.GatherRecord(r.handle, cams, cap=cap)
+        out = rec.replay()
+        torch.cuda.synchronize()
+        assert rec.n_slots == 13 * 8 * 64
+        assert torch.equal(rec.image, plain)
+        count = rec.count.cpu().numpy()
+        assert count.sum() == int(st[3]) == int(rec.stats[3])
+        assert np.array_equal(out[:, 0].cpu().numpy(), np.minimum(count, cap).astype(np.float32))
+        # every recorded offset lies inside its array
+        R = tiny_scene.R
+        nbl = tiny_scene.L // 8
+        recs = rec.rec.cpu().numpy().view(np.uint32)
+        k = np.arange(cap)[:, None]
+        valid = k < count[None, :]
+        planes = recs[..., :3][valid]
+        assert planes.max() + R * 8 + 16 <= 3 * R * R * 8
+        grid = recs[..., 3][valid]
+        assert (grid >> 13).max() < nbl ** 3 and (grid & 8191).max() < 9 * 9 * 9 * 8
+    finally:
+        r.close()
