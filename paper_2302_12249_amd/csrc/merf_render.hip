@@ -154,6 +154,11 @@ __device__ __forceinline__ int region_at(float3 o, float3 d, float t) {
     return region_of(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
 }
 
+// Number of lanes below this one whose bit is set in the wave mask m.
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 __device__ __forceinline__ float sigmoid(float x) { return __builtin_amdgcn_rcpf(1.0f + __expf(-x)); }
@@ -255,11 +260,18 @@ __device__ __forceinline__ Texels gather(const DevScene &sc, const Footprint &f)
     return x;
 }
 
-// One evaluated sample: gather, dequantise, decode, composite.
+// Shaded sample: 1 - alpha and, when alpha != 0, the sigmoids of the diffuse
+// colour and the features (Eq. 6).
+struct SampleResult {
+    float trans;
+    float sg[7];
+};
+
+// One evaluated sample: gather, dequantise, decode.
 // All offsets are 32-bit (the upload keeps every array below 2 GiB) and are
 // added to uniform base pointers, so no 64-bit address arithmetic runs per lane.
-template <bool kStats, bool kFeatF16>
-__device__ __forceinline__ void shade_sample(const DevScene &sc, float3 p, float delta, Accum &acc, Counters &cnt) {
+template <bool kFeatF16>
+__device__ __forceinline__ SampleResult eval_sample(const DevScene &sc, float3 p, float delta) {
     const Footprint f = footprint(sc, p);
     const Texels x = gather(sc, f);
     // texel words of the 20 texels (lo = channels 0..3, hi = 4..7) and their
@@ -311,55 +323,77 @@ __device__ __forceinline__ void shade_sample(const DevScene &sc, float3 p, float
         for (int i = 0; i < 20; ++i) s0 = fmaf(w[i], (float)byte_of(lo[i], 0), s0);
         s0 = fmaf(s0, md * (2.0f / 255.0f), -nsrc * md);
     }
+    SampleResult r;
     float tau = __expf(s0);                       // Eq. 6
-    float trans = __expf(-tau * delta);           // e^{-tau delta} = 1 - alpha (Eq. 1)
-    float alpha = 1.0f - trans;
-    if (kStats) ++cnt.evaluated;
-    if (alpha > 0.0f) {
-        if (kStats) ++cnt.contributing;
-        float s[7];
+    r.trans = __expf(-tau * delta);               // e^{-tau delta} = 1 - alpha (Eq. 1)
+    if (1.0f - r.trans > 0.0f) {
+        float sa[7];
 #pragma unroll
-        for (int c = 0; c < 7; ++c) s[c] = 0.0f;
+        for (int c = 0; c < 7; ++c) sa[c] = 0.0f;
         const float af = mf * (2.0f / 255.0f);
         if constexpr (kFeatF16) {
 #pragma unroll
             for (int i = 0; i < 20; ++i) {
 #pragma unroll
-                for (int c = 1; c < 4; ++c) s[c - 1] = fmaf(w[i], deq_f16(byte_of(lo[i], c), af, mf), s[c - 1]);
+                for (int c = 1; c < 4; ++c) sa[c - 1] = fmaf(w[i], deq_f16(byte_of(lo[i], c), af, mf), sa[c - 1]);
 #pragma unroll
-                for (int c = 0; c < 4; ++c) s[3 + c] = fmaf(w[i], deq_f16(byte_of(hi[i], c), af, mf), s[3 + c]);
+                for (int c = 0; c < 4; ++c) sa[3 + c] = fmaf(w[i], deq_f16(byte_of(hi[i], c), af, mf), sa[3 + c]);
             }
         } else {
 #pragma unroll
             for (int i = 0; i < 20; ++i) {
 #pragma unroll
-                for (int c = 1; c < 4; ++c) s[c - 1] = fmaf(w[i], (float)byte_of(lo[i], c), s[c - 1]);
+                for (int c = 1; c < 4; ++c) sa[c - 1] = fmaf(w[i], (float)byte_of(lo[i], c), sa[c - 1]);
 #pragma unroll
-                for (int c = 0; c < 4; ++c) s[3 + c] = fmaf(w[i], (float)byte_of(hi[i], c), s[3 + c]);
+                for (int c = 0; c < 4; ++c) sa[3 + c] = fmaf(w[i], (float)byte_of(hi[i], c), sa[3 + c]);
             }
 #pragma unroll
-            for (int c = 0; c < 7; ++c) s[c] = fmaf(s[c], af, -nsrc * mf);
+            for (int c = 0; c < 7; ++c) sa[c] = fmaf(sa[c], af, -nsrc * mf);
         }
-        float wt = acc.T * alpha;                 // Eq. 1-2
-        acc.cd0 = fmaf(wt, sigmoid(s[0]), acc.cd0);
-        acc.cd1 = fmaf(wt, sigmoid(s[1]), acc.cd1);
-        acc.cd2 = fmaf(wt, sigmoid(s[2]), acc.cd2);
-        acc.f0 = fmaf(wt, sigmoid(s[3]), acc.f0);
-        acc.f1 = fmaf(wt, sigmoid(s[4]), acc.f1);
-        acc.f2 = fmaf(wt, sigmoid(s[5]), acc.f2);
-        acc.f3 = fmaf(wt, sigmoid(s[6]), acc.f3);
-        acc.T *= trans;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) r.sg[c] = sigmoid(sa[c]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) r.sg[c] = 0.0f;
+    }
+    return r;
+}
+
+// Front-to-back compositing of one shaded sample (Eq. 1-2).
+template <bool kStats>
+__device__ __forceinline__ void composite(Accum &acc, const SampleResult &r, Counters &cnt) {
+    const float alpha = 1.0f - r.trans;
+    if (kStats) ++cnt.evaluated;
+    if (alpha > 0.0f) {
+        if (kStats) ++cnt.contributing;
+        const float wt = acc.T * alpha;
+        acc.cd0 = fmaf(wt, r.sg[0], acc.cd0);
+        acc.cd1 = fmaf(wt, r.sg[1], acc.cd1);
+        acc.cd2 = fmaf(wt, r.sg[2], acc.cd2);
+        acc.f0 = fmaf(wt, r.sg[3], acc.f0);
+        acc.f1 = fmaf(wt, r.sg[4], acc.f1);
+        acc.f2 = fmaf(wt, r.sg[5], acc.f2);
+        acc.f3 = fmaf(wt, r.sg[6], acc.f3);
+        acc.T *= r.trans;
     }
 }
 
 // March state of one straight contracted segment A -> B (region reg) that
-// covers the world parameters [ta, tb] of the ray.
+// covers the world parameters [ta, tb] of the ray (B itself is recomputed by
+// segment_end where needed).
 struct Segment {
-    float3 A, B, e;                 // contracted start, end, unit direction
+    float3 A, e;                    // contracted start, unit direction
     float len, iex, iey, iez;       // length; inverse direction (0 where e = 0)
     float tb;                       // world parameter of the end (kInf: last)
     int n, k, reg, reg_next;        // interval count, next interval, regions
 };
+
+// Contracted end point of the segment of region reg that ends at world
+// parameter tb (kInf: the limit point of the ray).
+__device__ __forceinline__ float3 segment_end(float3 o, float3 d, float tb, int reg) {
+    return tb < kInf ? map_region(reg, make_float3(fmaf(tb, d.x, o.x), fmaf(tb, d.y, o.y), fmaf(tb, d.z, o.z)))
+                     : limit_point(reg, d);
+}
 
 // Set up the segment of the ray that starts at world parameter ta in region
 // reg: find where the region next changes (Eq. 7 breakpoints), map both ends.
@@ -377,12 +411,11 @@ __device__ __forceinline__ void open_segment(float3 o, float3 d, float ta, int r
         cur = n1;
     }
     s.A = map_region(reg, make_float3(fmaf(ta, d.x, o.x), fmaf(ta, d.y, o.y), fmaf(ta, d.z, o.z)));
-    s.B = tb < kInf ? map_region(reg, make_float3(fmaf(tb, d.x, o.x), fmaf(tb, d.y, o.y), fmaf(tb, d.z, o.z)))
-                    : limit_point(reg, d);
+    const float3 B = segment_end(o, d, tb, reg);
     s.tb = tb;
     s.reg = reg;
     s.reg_next = reg_next;
-    float3 e = make_float3(s.B.x - s.A.x, s.B.y - s.A.y, s.B.z - s.A.z);
+    float3 e = make_float3(B.x - s.A.x, B.y - s.A.y, B.z - s.A.z);
     float len = sqrtf(e.x * e.x + e.y * e.y + e.z * e.z);
     s.k = 0;
     // contracted segments are at most a few units long; anything else is a
@@ -550,11 +583,19 @@ __device__ __forceinline__ float3 deferred_mlp_mfma(const float *__restrict__ W,
     return make_float3(xs[lane * Lds::kOut + 0], xs[lane * Lds::kOut + 1], xs[lane * Lds::kOut + 2]);
 }
 
+// Samples a lane may park ahead of its compositing, and the LDS of a wave:
+// the parking area (kQueue x 64 x (p, delta), kQueue x 64 x 8 results, the
+// 64-entry shading map) during the march, the MLP staging afterwards.
+constexpr int kQueue = 2;
+template <int kPrec>
+constexpr int kLdsFloats = MlpLds<kPrec>::kFloats > 12 * 64 * kQueue + 64 ? MlpLds<kPrec>::kFloats
+                                                                          : 12 * 64 * kQueue + 64;
+
 // kLevels: empty space is skipped with the occupancy levels themselves
 // (skip_mode 1) instead of the distance grid (skip_mode 0).
 template <bool kStats, int kMlpPrec, bool kFeatF16, bool kLevels>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_render(const DevScene sc, const RenderBatch rb) {
-    __shared__ float xs[MlpLds<kMlpPrec>::kFloats];
+    __shared__ float lds[kLdsFloats<kMlpPrec>];
     const int tile = xcd_remap((int)blockIdx.x, rb.total_tiles);
     int c = 0;
 #pragma unroll
@@ -590,18 +631,27 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     bool alive = active, terminated = false;
     float known[kMaxLevels] = {0.0f, 0.0f, 0.0f, 0.0f};   // per level: occupied up to this u
 
-    // Each round: every live lane advances to its next occupied sample (cheap
-    // skip iterations), then all lanes that found one shade it together, so
-    // the expensive gather-and-composite code runs with as many lanes as
-    // possible.
-    while (__any(alive)) {
-        bool found = false;
-        float3 p = make_float3(0.f, 0.f, 0.f);
-        float delta = 0.0f;
-        while (alive && !found) {
+    // The march runs ahead of the shading: every live lane finds up to kQueue
+    // occupied samples (cheap skip iterations) and parks them in LDS; then the
+    // wave shades up to 64 parked samples at once -- oldest first, whichever
+    // lane's ray they belong to -- so the expensive gather-and-decode code
+    // runs with as many lanes busy as possible; then every lane composites
+    // its own shaded samples in ray order.  Samples parked past an early
+    // termination are dropped, so the image is the one a one-sample-at-a-time
+    // march gives.
+    float4 *pq = reinterpret_cast<float4 *>(lds);             // [kQueue][64] parked (p, delta)
+    float4 *rs = pq + kQueue * 64;                            // [kQueue][64] x 2: shaded results
+    int *imap = reinterpret_cast<int *>(rs + 2 * kQueue * 64); // [64] shading slot -> parked entry
+    int pc = 0;                                               // samples parked by this lane
+    while (__any(alive || pc > 0)) {
+        // ---- march: live lanes park up to kQueue samples
+        while (alive && pc < kQueue) {
             if (s.k >= s.n) {
                 // segment done: continue in the next region, if any
-                if (!(s.tb < kInf) || nseg >= 8) { alive = false; break; }
+                if (!(s.tb < kInf) || nseg >= 8) {
+                    alive = false;
+                    break;
+                }
                 open_segment(o, d, s.tb, s.reg_next, istep, s);
                 ++nseg;
                 known[0] = known[1] = known[2] = known[3] = 0.0f;
@@ -610,7 +660,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
             const float u0 = (float)s.k * step;
             const float u1 = fminf(u0 + step, s.len);
             const float um = 0.5f * (u0 + u1);
-            p = make_float3(fmaf(um, s.e.x, s.A.x), fmaf(um, s.e.y, s.A.y), fmaf(um, s.e.z, s.A.z));
+            const float3 p = make_float3(fmaf(um, s.e.x, s.A.x), fmaf(um, s.e.y, s.A.y), fmaf(um, s.e.z, s.A.z));
             if (kStats) ++cnt.visited;
             // empty >= 0: the sample is in empty space, which the segment
             // leaves at parameter uexit.  A cell seen occupied stays known
@@ -679,12 +729,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
                 }
             }
             if (empty < 0) {
-                found = true;
-                delta = u1 - u0;
+                float delta = u1 - u0;
                 if (rb.delta_mode == 1) {
                     float3 y0 = make_float3(fmaf(u0, s.e.x, s.A.x), fmaf(u0, s.e.y, s.A.y), fmaf(u0, s.e.z, s.A.z));
                     float3 y1 = (s.k == s.n - 1)
-                                    ? s.B
+                                    ? segment_end(o, d, s.tb, s.reg)
                                     : make_float3(fmaf(u1, s.e.x, s.A.x), fmaf(u1, s.e.y, s.A.y), fmaf(u1, s.e.z, s.A.z));
                     bool at_inf = false;
                     if (s.reg != 0) {
@@ -701,7 +750,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
                         delta = sqrtf(dx * dx + dy * dy + dz * dz);
                     }
                 }
-                break;
+                pq[pc * 64 + lane] = make_float4(p.x, p.y, p.z, delta);
+                ++pc;
+                ++s.k;
+                continue;
             }
             // leave the empty cell
             // first lattice interval whose midpoint lies past the exit
@@ -709,27 +761,67 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
             int knext = kn > (float)s.n ? s.n : (int)fmaxf(kn, 0.0f);
             s.k = max(s.k + 1, knext);
         }
-        if (found) {
-            if (kStats && rb.rec) {
-                // measurement: record the texel offsets of this sample
-                const uint32_t k = cnt.evaluated;
-                if (k < (uint32_t)rb.rec_cap) {
-                    const Footprint f = footprint(sc, p);
-                    const uint32_t q = (uint32_t)tile * 64u + (uint32_t)lane;
-                    *reinterpret_cast<u32x4 *>(rb.rec + 4 * ((size_t)k * (size_t)rb.total_tiles * 64u + q)) =
-                        u32x4{f.op[0], f.op[1], f.op[2], (f.bi << 13) | f.ol};
+        // ---- shade: parked samples numbered level by level (all first
+        // samples, then all second ones ...), lane order within a level;
+        // slots past 64 wait for the next round
+        int total = 0;
+#pragma unroll
+        for (int j = 0; j < kQueue; ++j) {
+            const int item = total + lanes_below(__ballot(pc > j));
+            if (pc > j && item < 64) imap[item] = j * 64 + lane;
+            total += __popcll(__ballot(pc > j));
+        }
+        __syncthreads();
+        if (lane < total) {
+            const int e = imap[lane];
+            const float4 q = pq[e];
+            const SampleResult r = eval_sample<kFeatF16>(sc, make_float3(q.x, q.y, q.z), q.w);
+            rs[2 * e] = make_float4(r.trans, r.sg[0], r.sg[1], r.sg[2]);
+            rs[2 * e + 1] = make_float4(r.sg[3], r.sg[4], r.sg[5], r.sg[6]);
+        }
+        __syncthreads();
+        // ---- composite this lane's shaded samples in ray order
+        int done = 0, before = 0;
+#pragma unroll
+        for (int j = 0; j < kQueue; ++j) {
+            const int item = before + lanes_below(__ballot(pc > j));
+            before += __popcll(__ballot(pc > j));
+            if (j < pc && item < 64 && !terminated) {
+                const int e = j * 64 + lane;
+                if (kStats && rb.rec) {
+                    // measurement: record the texel offsets of this sample
+                    const uint32_t k = cnt.evaluated;
+                    if (k < (uint32_t)rb.rec_cap) {
+                        const float4 q = pq[e];
+                        const Footprint f = footprint(sc, make_float3(q.x, q.y, q.z));
+                        const uint32_t qs = (uint32_t)tile * 64u + (uint32_t)lane;
+                        *reinterpret_cast<u32x4 *>(rb.rec + 4 * ((size_t)k * (size_t)rb.total_tiles * 64u + qs)) =
+                            u32x4{f.op[0], f.op[1], f.op[2], (f.bi << 13) | f.ol};
+                    }
+                }
+                const float4 ra = rs[2 * e], rbv = rs[2 * e + 1];
+                const SampleResult r = {ra.x, {ra.y, ra.z, ra.w, rbv.x, rbv.y, rbv.z, rbv.w}};
+                composite<kStats>(acc, r, cnt);
+                ++done;
+                if (acc.T < rb.t_min) {          // early termination (Sec. 6)
+                    alive = false;
+                    terminated = true;
                 }
             }
-            shade_sample<kStats, kFeatF16>(sc, p, delta, acc, cnt);
-            ++s.k;
-            if (acc.T < rb.t_min) {          // early termination (Sec. 6)
-                alive = false;
-                terminated = true;
-            }
         }
+        // ---- keep the samples not shaded yet, in order
+        if (terminated) {
+            pc = 0;
+        } else if (done > 0) {
+#pragma unroll
+            for (int j = 0; j + 1 < kQueue; ++j)
+                if (j + done < pc) pq[j * 64 + lane] = pq[(j + done) * 64 + lane];
+            pc -= done;
+        }
+        __syncthreads();
     }
 
-    const float3 h = deferred_mlp_mfma<kMlpPrec>(sc.mlp, xs, acc, d);
+    const float3 h = deferred_mlp_mfma<kMlpPrec>(sc.mlp, lds, acc, d);
     if (active) {
         float4 rgba = make_float4(acc.cd0 + h.x, acc.cd1 + h.y, acc.cd2 + h.z, 1.0f - acc.T);
         *reinterpret_cast<float4 *>(cam.out + ((int64_t)py * cam.width + px) * 4) = rgba;
