@@ -586,7 +586,7 @@ __device__ __forceinline__ float3 deferred_mlp_mfma(const float *__restrict__ W,
 // Samples a lane may park ahead of its compositing, and the LDS of a wave:
 // the parking area (kQueue x 64 x (p, delta), kQueue x 64 x 8 results, the
 // 64-entry shading map) during the march, the MLP staging afterwards.
-constexpr int kQueue = 2;
+constexpr int kQueue = 3;
 template <int kPrec>
 constexpr int kLdsFloats = MlpLds<kPrec>::kFloats > 12 * 64 * kQueue + 64 ? MlpLds<kPrec>::kFloats
                                                                           : 12 * 64 * kQueue + 64;
@@ -644,122 +644,132 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     int *imap = reinterpret_cast<int *>(rs + 2 * kQueue * 64); // [64] shading slot -> parked entry
     int pc = 0;                                               // samples parked by this lane
     while (__any(alive || pc > 0)) {
-        // ---- march: live lanes park up to kQueue samples
-        while (alive && pc < kQueue) {
-            if (s.k >= s.n) {
-                // segment done: continue in the next region, if any
-                if (!(s.tb < kInf) || nseg >= 8) {
-                    alive = false;
-                    break;
-                }
-                open_segment(o, d, s.tb, s.reg_next, istep, s);
-                ++nseg;
-                known[0] = known[1] = known[2] = known[3] = 0.0f;
-                continue;
-            }
-            const float u0 = (float)s.k * step;
-            const float u1 = fminf(u0 + step, s.len);
-            const float um = 0.5f * (u0 + u1);
-            const float3 p = make_float3(fmaf(um, s.e.x, s.A.x), fmaf(um, s.e.y, s.A.y), fmaf(um, s.e.z, s.A.z));
-            if (kStats) ++cnt.visited;
-            // empty >= 0: the sample is in empty space, which the segment
-            // leaves at parameter uexit.  A cell seen occupied stays known
-            // until the segment leaves it (its exit minus the guard), so later
-            // samples inside it need no lookup.
-            int empty = -1;
-            float uexit = 0.0f;
-            if constexpr (!kLevels) {
-                // distance grid: a cell at Chebyshev distance D > 0 from the
-                // nearest occupied cell is the centre of an empty cube of
-                // 2D - 1 cells; leave the whole cube (D = 0: occupied, the
-                // cube is the cell itself)
-                if (!(um < known[0])) {
-                    const int r = sc.dist_res;
-                    const float os = (float)r * 0.25f;
-                    const int qx = clampi((int)floorf((p.x + 2.0f) * os), 0, r - 1);
-                    const int qy = clampi((int)floorf((p.y + 2.0f) * os), 0, r - 1);
-                    const int qz = clampi((int)floorf((p.z + 2.0f) * os), 0, r - 1);
-                    if (kStats) ++cnt.occ_lookups;
-                    const int D = sc.dist[((uint32_t)qz * r + qy) * r + qx];
-                    const int ext = D > 0 ? D - 1 : 0;
-                    const float h = sc.dist_cell;
-                    const float bx = (float)(s.e.x > 0.0f ? qx + ext + 1 : qx - ext) * h - 2.0f;
-                    const float by = (float)(s.e.y > 0.0f ? qy + ext + 1 : qy - ext) * h - 2.0f;
-                    const float bz = (float)(s.e.z > 0.0f ? qz + ext + 1 : qz - ext) * h - 2.0f;
-                    const float tx = s.e.x != 0.0f ? (bx - s.A.x) * s.iex : kInf;
-                    const float ty = s.e.y != 0.0f ? (by - s.A.y) * s.iey : kInf;
-                    const float tz = s.e.z != 0.0f ? (bz - s.A.z) * s.iez : kInf;
-                    const float ue = fminf(tx, fminf(ty, tz));
-                    if (D == 0) {
-                        known[0] = ue - kSkipGuard;
-                    } else {
-                        empty = 0;
-                        uexit = ue;
-                    }
-                }
-            } else {
-                // the occupancy levels, coarse to fine: stop at the first
-                // empty level and leave its cell
+        // ---- march: live lanes park up to kQueue samples, one step per
+        // pass; the wave stops once 64 samples are parked (a round shades no
+        // more), so slow lanes do not hold the others back
+        for (;;) {
+            const bool want = alive && pc < kQueue;
+            int parked = 0;
 #pragma unroll
-                for (int l = 0; l < kMaxLevels; ++l) {
-                    if (l < sc.occ_levels && empty < 0 && !(um < known[l])) {
-                        const int rl = sc.occ_res[l];
-                        const float os = (float)rl * 0.25f;
-                        const int qx = clampi((int)floorf((p.x + 2.0f) * os), 0, rl - 1);
-                        const int qy = clampi((int)floorf((p.y + 2.0f) * os), 0, rl - 1);
-                        const int qz = clampi((int)floorf((p.z + 2.0f) * os), 0, rl - 1);
+            for (int j = 0; j < kQueue; ++j) parked += __popcll(__ballot(pc > j));
+            if (!__any(want) || parked >= 64) break;
+            if (!want) continue;
+            do {   // one march step: break and continue both end it
+                if (s.k >= s.n) {
+                    // segment done: continue in the next region, if any
+                    if (!(s.tb < kInf) || nseg >= 8) {
+                        alive = false;
+                        break;
+                    }
+                    open_segment(o, d, s.tb, s.reg_next, istep, s);
+                    ++nseg;
+                    known[0] = known[1] = known[2] = known[3] = 0.0f;
+                    continue;
+                }
+                const float u0 = (float)s.k * step;
+                const float u1 = fminf(u0 + step, s.len);
+                const float um = 0.5f * (u0 + u1);
+                const float3 p = make_float3(fmaf(um, s.e.x, s.A.x), fmaf(um, s.e.y, s.A.y), fmaf(um, s.e.z, s.A.z));
+                if (kStats) ++cnt.visited;
+                // empty >= 0: the sample is in empty space, which the segment
+                // leaves at parameter uexit.  A cell seen occupied stays known
+                // until the segment leaves it (its exit minus the guard), so later
+                // samples inside it need no lookup.
+                int empty = -1;
+                float uexit = 0.0f;
+                if constexpr (!kLevels) {
+                    // distance grid: a cell at Chebyshev distance D > 0 from the
+                    // nearest occupied cell is the centre of an empty cube of
+                    // 2D - 1 cells; leave the whole cube (D = 0: occupied, the
+                    // cube is the cell itself)
+                    if (!(um < known[0])) {
+                        const int r = sc.dist_res;
+                        const float os = (float)r * 0.25f;
+                        const int qx = clampi((int)floorf((p.x + 2.0f) * os), 0, r - 1);
+                        const int qy = clampi((int)floorf((p.y + 2.0f) * os), 0, r - 1);
+                        const int qz = clampi((int)floorf((p.z + 2.0f) * os), 0, r - 1);
                         if (kStats) ++cnt.occ_lookups;
-                        const bool occ = sc.occ[l][((uint32_t)qz * rl + qy) * rl + qx] != 0;
-                        // exit parameter of this cell along the segment (slab test)
-                        const float h = sc.occ_cell[l];
-                        const float bx = (float)(s.e.x > 0.0f ? qx + 1 : qx) * h - 2.0f;
-                        const float by = (float)(s.e.y > 0.0f ? qy + 1 : qy) * h - 2.0f;
-                        const float bz = (float)(s.e.z > 0.0f ? qz + 1 : qz) * h - 2.0f;
+                        const int D = sc.dist[((uint32_t)qz * r + qy) * r + qx];
+                        const int ext = D > 0 ? D - 1 : 0;
+                        const float h = sc.dist_cell;
+                        const float bx = (float)(s.e.x > 0.0f ? qx + ext + 1 : qx - ext) * h - 2.0f;
+                        const float by = (float)(s.e.y > 0.0f ? qy + ext + 1 : qy - ext) * h - 2.0f;
+                        const float bz = (float)(s.e.z > 0.0f ? qz + ext + 1 : qz - ext) * h - 2.0f;
                         const float tx = s.e.x != 0.0f ? (bx - s.A.x) * s.iex : kInf;
                         const float ty = s.e.y != 0.0f ? (by - s.A.y) * s.iey : kInf;
                         const float tz = s.e.z != 0.0f ? (bz - s.A.z) * s.iez : kInf;
                         const float ue = fminf(tx, fminf(ty, tz));
-                        if (occ) {
-                            known[l] = ue - kSkipGuard;
+                        if (D == 0) {
+                            known[0] = ue - kSkipGuard;
                         } else {
-                            empty = l;
+                            empty = 0;
                             uexit = ue;
                         }
                     }
-                }
-            }
-            if (empty < 0) {
-                float delta = u1 - u0;
-                if (rb.delta_mode == 1) {
-                    float3 y0 = make_float3(fmaf(u0, s.e.x, s.A.x), fmaf(u0, s.e.y, s.A.y), fmaf(u0, s.e.z, s.A.z));
-                    float3 y1 = (s.k == s.n - 1)
-                                    ? segment_end(o, d, s.tb, s.reg)
-                                    : make_float3(fmaf(u1, s.e.x, s.A.x), fmaf(u1, s.e.y, s.A.y), fmaf(u1, s.e.z, s.A.z));
-                    bool at_inf = false;
-                    if (s.reg != 0) {
-                        const int jj = (s.reg - 1) >> 1;
-                        const float sg = ((s.reg - 1) & 1) ? -1.0f : 1.0f;
-                        const float y1j = jj == 0 ? y1.x : (jj == 1 ? y1.y : y1.z);
-                        at_inf = sg * y1j >= 2.0f;
+                } else {
+                    // the occupancy levels, coarse to fine: stop at the first
+                    // empty level and leave its cell
+#pragma unroll
+                    for (int l = 0; l < kMaxLevels; ++l) {
+                        if (l < sc.occ_levels && empty < 0 && !(um < known[l])) {
+                            const int rl = sc.occ_res[l];
+                            const float os = (float)rl * 0.25f;
+                            const int qx = clampi((int)floorf((p.x + 2.0f) * os), 0, rl - 1);
+                            const int qy = clampi((int)floorf((p.y + 2.0f) * os), 0, rl - 1);
+                            const int qz = clampi((int)floorf((p.z + 2.0f) * os), 0, rl - 1);
+                            if (kStats) ++cnt.occ_lookups;
+                            const bool occ = sc.occ[l][((uint32_t)qz * rl + qy) * rl + qx] != 0;
+                            // exit parameter of this cell along the segment (slab test)
+                            const float h = sc.occ_cell[l];
+                            const float bx = (float)(s.e.x > 0.0f ? qx + 1 : qx) * h - 2.0f;
+                            const float by = (float)(s.e.y > 0.0f ? qy + 1 : qy) * h - 2.0f;
+                            const float bz = (float)(s.e.z > 0.0f ? qz + 1 : qz) * h - 2.0f;
+                            const float tx = s.e.x != 0.0f ? (bx - s.A.x) * s.iex : kInf;
+                            const float ty = s.e.y != 0.0f ? (by - s.A.y) * s.iey : kInf;
+                            const float tz = s.e.z != 0.0f ? (bz - s.A.z) * s.iez : kInf;
+                            const float ue = fminf(tx, fminf(ty, tz));
+                            if (occ) {
+                                known[l] = ue - kSkipGuard;
+                            } else {
+                                empty = l;
+                                uexit = ue;
+                            }
+                        }
                     }
-                    if (at_inf) {
-                        delta = kInf;
-                    } else {
-                        float3 x0 = unmap_region(s.reg, y0), x1 = unmap_region(s.reg, y1);
-                        float dx = x1.x - x0.x, dy = x1.y - x0.y, dz = x1.z - x0.z;
-                        delta = sqrtf(dx * dx + dy * dy + dz * dz);
-                    }
                 }
-                pq[pc * 64 + lane] = make_float4(p.x, p.y, p.z, delta);
-                ++pc;
-                ++s.k;
-                continue;
-            }
-            // leave the empty cell
-            // first lattice interval whose midpoint lies past the exit
-            float kn = floorf((uexit - kSkipGuard) * istep - 0.5f) + 1.0f;
-            int knext = kn > (float)s.n ? s.n : (int)fmaxf(kn, 0.0f);
-            s.k = max(s.k + 1, knext);
+                if (empty < 0) {
+                    float delta = u1 - u0;
+                    if (rb.delta_mode == 1) {
+                        float3 y0 = make_float3(fmaf(u0, s.e.x, s.A.x), fmaf(u0, s.e.y, s.A.y), fmaf(u0, s.e.z, s.A.z));
+                        float3 y1 = (s.k == s.n - 1)
+                                        ? segment_end(o, d, s.tb, s.reg)
+                                        : make_float3(fmaf(u1, s.e.x, s.A.x), fmaf(u1, s.e.y, s.A.y), fmaf(u1, s.e.z, s.A.z));
+                        bool at_inf = false;
+                        if (s.reg != 0) {
+                            const int jj = (s.reg - 1) >> 1;
+                            const float sg = ((s.reg - 1) & 1) ? -1.0f : 1.0f;
+                            const float y1j = jj == 0 ? y1.x : (jj == 1 ? y1.y : y1.z);
+                            at_inf = sg * y1j >= 2.0f;
+                        }
+                        if (at_inf) {
+                            delta = kInf;
+                        } else {
+                            float3 x0 = unmap_region(s.reg, y0), x1 = unmap_region(s.reg, y1);
+                            float dx = x1.x - x0.x, dy = x1.y - x0.y, dz = x1.z - x0.z;
+                            delta = sqrtf(dx * dx + dy * dy + dz * dz);
+                        }
+                    }
+                    pq[pc * 64 + lane] = make_float4(p.x, p.y, p.z, delta);
+                    ++pc;
+                    ++s.k;
+                    continue;
+                }
+                // leave the empty cell
+                // first lattice interval whose midpoint lies past the exit
+                float kn = floorf((uexit - kSkipGuard) * istep - 0.5f) + 1.0f;
+                int knext = kn > (float)s.n ? s.n : (int)fmaxf(kn, 0.0f);
+                s.k = max(s.k + 1, knext);
+            } while (false);
         }
         // ---- shade: parked samples numbered level by level (all first
         // samples, then all second ones ...), lane order within a level;
