@@ -154,6 +154,13 @@ __device__ __forceinline__ int region_at(float3 o, float3 d, float t) {
     return region_of(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
 }
 
+// Byte offset of cell (x, y, z) of an r^3 z-major grid; every factor is
+// below 2^24 (r <= 1024), so the products are 24-bit multiplies.
+__device__ __forceinline__ uint32_t cell_offset(int x, int y, int z, int r) {
+    const uint32_t m = 0xffffffu, ur = (uint32_t)r & m;
+    return (((((uint32_t)z & m) * ur + (uint32_t)y) & m) * ur) + (uint32_t)x;
+}
+
 // Number of lanes below this one whose bit is set in the wave mask m.
 __device__ __forceinline__ int lanes_below(uint64_t m) {
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -206,10 +213,10 @@ struct Footprint {
 __device__ __forceinline__ Footprint footprint(const DevScene &sc, float3 p) {
     Footprint f;
     // ---- three planes, bilinear: P_x(y, z), P_y(x, z), P_z(x, y)
-    const float ps = (float)sc.R * 0.25f, pmax = (float)(sc.R - 1);
-    float hx = fminf(fmaxf(fmaf(p.x + 2.0f, ps, -0.5f), 0.0f), pmax);
-    float hy = fminf(fmaxf(fmaf(p.y + 2.0f, ps, -0.5f), 0.0f), pmax);
-    float hz = fminf(fmaxf(fmaf(p.z + 2.0f, ps, -0.5f), 0.0f), pmax);
+    const float ps = (float)sc.R * 0.25f, ps2 = 2.0f * ps - 0.5f, pmax = (float)(sc.R - 1);
+    float hx = __builtin_amdgcn_fmed3f(fmaf(p.x, ps, ps2), 0.0f, pmax);
+    float hy = __builtin_amdgcn_fmed3f(fmaf(p.y, ps, ps2), 0.0f, pmax);
+    float hz = __builtin_amdgcn_fmed3f(fmaf(p.z, ps, ps2), 0.0f, pmax);
     int jx = min((int)hx, sc.R - 2), jy = min((int)hy, sc.R - 2), jz = min((int)hz, sc.R - 2);
     f.ex = hx - (float)jx; f.ey = hy - (float)jy; f.ez = hz - (float)jz;
     const uint32_t row = (uint32_t)sc.R * kChannels, plane = (uint32_t)sc.R * row;
@@ -218,10 +225,10 @@ __device__ __forceinline__ Footprint footprint(const DevScene &sc, float3 p) {
     f.op[1] = plane + (uint32_t)jz * row + (uint32_t)jx * kChannels;
     f.op[2] = 2u * plane + (uint32_t)jy * row + (uint32_t)jx * kChannels;
     // ---- sparse 3D grid, trilinear inside one apron brick
-    const float gs = (float)sc.L * 0.25f, gmax = (float)(sc.L - 1);
-    float gx = fminf(fmaxf(fmaf(p.x + 2.0f, gs, -0.5f), 0.0f), gmax);
-    float gy = fminf(fmaxf(fmaf(p.y + 2.0f, gs, -0.5f), 0.0f), gmax);
-    float gz = fminf(fmaxf(fmaf(p.z + 2.0f, gs, -0.5f), 0.0f), gmax);
+    const float gs = (float)sc.L * 0.25f, gs2 = 2.0f * gs - 0.5f, gmax = (float)(sc.L - 1);
+    float gx = __builtin_amdgcn_fmed3f(fmaf(p.x, gs, gs2), 0.0f, gmax);
+    float gy = __builtin_amdgcn_fmed3f(fmaf(p.y, gs, gs2), 0.0f, gmax);
+    float gz = __builtin_amdgcn_fmed3f(fmaf(p.z, gs, gs2), 0.0f, gmax);
     int ix = min((int)gx, sc.L - 2), iy = min((int)gy, sc.L - 2), iz = min((int)gz, sc.L - 2);
     f.fx = gx - (float)ix; f.fy = gy - (float)iy; f.fz = gz - (float)iz;
     f.bi = ((uint32_t)(iz >> 3) * sc.nbl + (uint32_t)(iy >> 3)) * sc.nbl + (uint32_t)(ix >> 3);
@@ -383,7 +390,7 @@ __device__ __forceinline__ void composite(Accum &acc, const SampleResult &r, Cou
 // segment_end where needed).
 struct Segment {
     float3 A, e;                    // contracted start, unit direction
-    float len, iex, iey, iez;       // length; inverse direction (0 where e = 0)
+    float len, iex, iey, iez;       // length; inverse direction (+-inf where e = +-0)
     float tb;                       // world parameter of the end (kInf: last)
     int n, k, reg, reg_next;        // interval count, next interval, regions
 };
@@ -430,9 +437,11 @@ __device__ __forceinline__ void open_segment(float3 o, float3 d, float ta, int r
     s.e = e;
     s.len = len;
     s.n = (int)ceilf(len * istep);
-    s.iex = e.x != 0.0f ? rcp(e.x) : 0.0f;
-    s.iey = e.y != 0.0f ? rcp(e.y) : 0.0f;
-    s.iez = e.z != 0.0f ? rcp(e.z) : 0.0f;
+    // rcp(+-0) = +-inf: the slab tests below then give +inf (or NaN, which
+    // fminf ignores) for an axis the segment does not move along
+    s.iex = rcp(e.x);
+    s.iey = rcp(e.y);
+    s.iez = rcp(e.z);
 }
 
 // Deferred MLP (Eq. 3, App. B) for the 64 pixels of a wave on the matrix
@@ -684,20 +693,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
                     // cube is the cell itself)
                     if (!(um < known[0])) {
                         const int r = sc.dist_res;
-                        const float os = (float)r * 0.25f;
-                        const int qx = clampi((int)floorf((p.x + 2.0f) * os), 0, r - 1);
-                        const int qy = clampi((int)floorf((p.y + 2.0f) * os), 0, r - 1);
-                        const int qz = clampi((int)floorf((p.z + 2.0f) * os), 0, r - 1);
+                        // cell of p: (p + 2) r / 4 rounded down; contracted
+                        // points have p >= -2 up to rounding, so truncation
+                        // equals the floor and no lower clamp is needed
+                        const float os = (float)r * 0.25f, os2 = 2.0f * os;
+                        const int qx = min((int)fmaf(p.x, os, os2), r - 1);
+                        const int qy = min((int)fmaf(p.y, os, os2), r - 1);
+                        const int qz = min((int)fmaf(p.z, os, os2), r - 1);
                         if (kStats) ++cnt.occ_lookups;
-                        const int D = sc.dist[((uint32_t)qz * r + qy) * r + qx];
+                        const int D = load_at<uint8_t>(sc.dist, cell_offset(qx, qy, qz, r));
                         const int ext = D > 0 ? D - 1 : 0;
                         const float h = sc.dist_cell;
-                        const float bx = (float)(s.e.x > 0.0f ? qx + ext + 1 : qx - ext) * h - 2.0f;
-                        const float by = (float)(s.e.y > 0.0f ? qy + ext + 1 : qy - ext) * h - 2.0f;
-                        const float bz = (float)(s.e.z > 0.0f ? qz + ext + 1 : qz - ext) * h - 2.0f;
-                        const float tx = s.e.x != 0.0f ? (bx - s.A.x) * s.iex : kInf;
-                        const float ty = s.e.y != 0.0f ? (by - s.A.y) * s.iey : kInf;
-                        const float tz = s.e.z != 0.0f ? (bz - s.A.z) * s.iez : kInf;
+                        const float bx = (float)(s.iex > 0.0f ? qx + ext + 1 : qx - ext) * h - 2.0f;
+                        const float by = (float)(s.iey > 0.0f ? qy + ext + 1 : qy - ext) * h - 2.0f;
+                        const float bz = (float)(s.iez > 0.0f ? qz + ext + 1 : qz - ext) * h - 2.0f;
+                        const float tx = (bx - s.A.x) * s.iex;
+                        const float ty = (by - s.A.y) * s.iey;
+                        const float tz = (bz - s.A.z) * s.iez;
                         const float ue = fminf(tx, fminf(ty, tz));
                         if (D == 0) {
                             known[0] = ue - kSkipGuard;
@@ -713,20 +725,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
                     for (int l = 0; l < kMaxLevels; ++l) {
                         if (l < sc.occ_levels && empty < 0 && !(um < known[l])) {
                             const int rl = sc.occ_res[l];
-                            const float os = (float)rl * 0.25f;
-                            const int qx = clampi((int)floorf((p.x + 2.0f) * os), 0, rl - 1);
-                            const int qy = clampi((int)floorf((p.y + 2.0f) * os), 0, rl - 1);
-                            const int qz = clampi((int)floorf((p.z + 2.0f) * os), 0, rl - 1);
+                            const float os = (float)rl * 0.25f, os2 = 2.0f * os;
+                            const int qx = min((int)fmaf(p.x, os, os2), rl - 1);
+                            const int qy = min((int)fmaf(p.y, os, os2), rl - 1);
+                            const int qz = min((int)fmaf(p.z, os, os2), rl - 1);
                             if (kStats) ++cnt.occ_lookups;
-                            const bool occ = sc.occ[l][((uint32_t)qz * rl + qy) * rl + qx] != 0;
+                            const bool occ = load_at<uint8_t>(sc.occ[l], cell_offset(qx, qy, qz, rl)) != 0;
                             // exit parameter of this cell along the segment (slab test)
                             const float h = sc.occ_cell[l];
-                            const float bx = (float)(s.e.x > 0.0f ? qx + 1 : qx) * h - 2.0f;
-                            const float by = (float)(s.e.y > 0.0f ? qy + 1 : qy) * h - 2.0f;
-                            const float bz = (float)(s.e.z > 0.0f ? qz + 1 : qz) * h - 2.0f;
-                            const float tx = s.e.x != 0.0f ? (bx - s.A.x) * s.iex : kInf;
-                            const float ty = s.e.y != 0.0f ? (by - s.A.y) * s.iey : kInf;
-                            const float tz = s.e.z != 0.0f ? (bz - s.A.z) * s.iez : kInf;
+                            const float bx = (float)(s.iex > 0.0f ? qx + 1 : qx) * h - 2.0f;
+                            const float by = (float)(s.iey > 0.0f ? qy + 1 : qy) * h - 2.0f;
+                            const float bz = (float)(s.iez > 0.0f ? qz + 1 : qz) * h - 2.0f;
+                            const float tx = (bx - s.A.x) * s.iex;
+                            const float ty = (by - s.A.y) * s.iey;
+                            const float tz = (bz - s.A.z) * s.iez;
                             const float ue = fminf(tx, fminf(ty, tz));
                             if (occ) {
                                 known[l] = ue - kSkipGuard;
