@@ -112,9 +112,9 @@ typedef struct {
     int32_t feat_prec;                    /* 0 = codes interpolated in fp32; 1 = every code
                                              dequantised to float16 first (sums stay fp32) */
     int32_t skip_mode;                    /* empty-space skipping, same image either way:
-                                             0 = distance grid derived from the occupancy
-                                             levels at upload (the largest empty cube around
-                                             a sample is left in one step);
+                                             0 = empty-space grid derived from the occupancy
+                                             levels at upload (the largest empty cube ahead
+                                             of a sample is left in one step);
                                              1 = the levels themselves, coarse to fine,
                                              leaving one empty cell per step (Sec. 6) */
     uint64_t *stats_dev;                  /* NULL, or device uint64[8] to which the render
@@ -215,6 +215,21 @@ int merf_occupancy_pyramid(const uint8_t *mask_dev, int32_t res, const int32_t *
  */
 int merf_distance_grid(const uint8_t *const *occ_dev, const int32_t *res, int32_t n_levels, uint8_t *out_dev,
                        void *hip_stream);
+
+/*
+ * Octant form of the empty-space grid (what the upload builds for skip_mode
+ * 0 when the finest occupancy resolution is at most 256).  Same inputs as
+ * merf_distance_grid; out_dev (device, 8 r^3 bytes, caller-owned) receives
+ * eight grids, octant o = (bit 0: -x, bit 1: -y, bit 2: -z) at o r^3: for each
+ * finest cell, the largest E <= 255 such that the cube of E cells on a side
+ * with a corner at the cell, extending in the octant's directions (clipped to
+ * the grid), holds no cell that every level marks occupied; 0 for such a cell
+ * itself.  Allocates 5 r^3 bytes of device scratch, runs on hip_stream and
+ * returns once the grids are complete.
+ * Errors: as merf_distance_grid.
+ */
+int merf_octant_extent_grid(const uint8_t *const *occ_dev, const int32_t *res, int32_t n_levels, uint8_t *out_dev,
+                            void *hip_stream);
 
 #ifdef __cplusplus
 }

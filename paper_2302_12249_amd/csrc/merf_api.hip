@@ -158,7 +158,7 @@ Layout make_layout(const merf_scene_desc *d, int64_t nbricks) {
         off = align_up(off + r * r * r, 256);
     }
     const size_t rf = (size_t)d->occ_res[d->occ_levels - 1];
-    o.dist = off; off = align_up(off + rf * rf * rf, 256);
+    o.dist = off; off = align_up(off + (rf <= (size_t)kOctMaxRes ? 8 : 1) * rf * rf * rf, 256);
     o.mlp = off; off = align_up(off + kMlpParams * sizeof(float), 256);
     o.total = off;
     return o;
@@ -313,7 +313,10 @@ int merf_scene_upload(const merf_scene_desc *desc, merf_scene_t *out) {
                  s_pos = s_index + align_up((size_t)nbl * nbl * nbl * sizeof(int32_t), 256),
                  s_dist0 = s_pos + align_up(std::max<size_t>(bpos.size(), 1) * sizeof(int32_t), 256);
     const size_t rf = (size_t)desc->occ_res[desc->occ_levels - 1], nf = rf * rf * rf;
-    const size_t s_dist1 = s_dist0 + align_up(nf, 256), staging = s_dist1 + align_up(nf, 256);
+    const bool octants = rf <= (size_t)kOctMaxRes;
+    // distance scratch: seed + second byte grid, or seed + int32 prefix sums
+    const size_t s_dist1 = s_dist0 + align_up(nf, 256),
+                 staging = s_dist1 + align_up(octants ? nf * sizeof(int32_t) : nf, 256);
     void *base = nullptr, *stage = nullptr;
     hipError_t e = hipMalloc(&base, total);
     if (e == hipSuccess) e = hipMalloc(&stage, staging);
@@ -354,7 +357,9 @@ int merf_scene_upload(const merf_scene_desc *desc, merf_scene_t *out) {
             lv.occ[l] = dev(o_occ[l]);
             lv.res[l] = desc->occ_res[l];
         }
-        e = launch_distance_grid(lv, stg(s_dist0), stg(s_dist1), dev(lay.dist), nullptr);
+        e = octants ? launch_octant_extents(lv, stg(s_dist0), reinterpret_cast<int32_t *>(stg(s_dist1)),
+                                            dev(lay.dist), nullptr)
+                    : launch_distance_grid(lv, stg(s_dist0), stg(s_dist1), dev(lay.dist), nullptr);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     (void)hipFree(stage);
@@ -380,6 +385,7 @@ int merf_scene_upload(const merf_scene_desc *desc, merf_scene_t *out) {
     }
     ds.dist = dev(lay.dist);
     ds.dist_res = (int32_t)rf;
+    ds.dist_oct_stride = octants ? (uint32_t)nf : 0u;
     ds.dist_cell = 4.0f / (float)rf;
     ds.mlp = reinterpret_cast<const float *>(dev(o_mlp));
     ds.L = L > 0 ? L : kBlock;            // stand-ins, see DevScene
@@ -478,13 +484,15 @@ int merf_occupancy_pyramid(const uint8_t *mask_dev, int32_t res, const int32_t *
     return MERF_OK;
 }
 
-int merf_distance_grid(const uint8_t *const *occ_dev, const int32_t *res, int32_t n_levels, uint8_t *out_dev,
-                       void *hip_stream) {
-    clear_error();
+namespace {
+
+// Checks and packs the occupancy levels of the distance-grid entry points.
+int occ_levels_arg(const uint8_t *const *occ_dev, const int32_t *res, int32_t n_levels, const uint8_t *out_dev,
+                   OccLevels &lv) {
     if (n_levels < 1 || n_levels > kMaxLevels)
         return fail(MERF_E_INVALID, "n_levels %d not in [1, %d]", n_levels, kMaxLevels);
     if (!occ_dev || !res || !out_dev) return fail(MERF_E_INVALID, "NULL buffer");
-    OccLevels lv{};
+    lv = OccLevels{};
     lv.n = n_levels;
     for (int l = 0; l < n_levels; ++l) {
         if (res[l] < 1 || res[l] > kMaxDistRes) return fail(MERF_E_INVALID, "res[%d] = %d not in [1, %d]", l, res[l], kMaxDistRes);
@@ -494,6 +502,17 @@ int merf_distance_grid(const uint8_t *const *occ_dev, const int32_t *res, int32_
         lv.occ[l] = occ_dev[l];
         lv.res[l] = res[l];
     }
+    return MERF_OK;
+}
+
+}  // namespace
+
+int merf_distance_grid(const uint8_t *const *occ_dev, const int32_t *res, int32_t n_levels, uint8_t *out_dev,
+                       void *hip_stream) {
+    clear_error();
+    OccLevels lv;
+    int rc = occ_levels_arg(occ_dev, res, n_levels, out_dev, lv);
+    if (rc) return rc;
     const size_t r = (size_t)res[n_levels - 1], n = r * r * r;
     void *tmp = nullptr;
     hipError_t e = hipMalloc(&tmp, 2 * align_up(n, 256));
@@ -507,6 +526,30 @@ int merf_distance_grid(const uint8_t *const *occ_dev, const int32_t *res, int32_
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     (void)hipFree(tmp);
     if (e != hipSuccess) return hip_fail(e, "distance grid");
+    return MERF_OK;
+}
+
+int merf_octant_extent_grid(const uint8_t *const *occ_dev, const int32_t *res, int32_t n_levels, uint8_t *out_dev,
+                            void *hip_stream) {
+    clear_error();
+    OccLevels lv;
+    int rc = occ_levels_arg(occ_dev, res, n_levels, out_dev, lv);
+    if (rc) return rc;
+    const size_t r = (size_t)res[n_levels - 1], n = r * r * r;
+    const size_t bytes = align_up(n, 256) + align_up(n * sizeof(int32_t), 256);
+    void *tmp = nullptr;
+    hipError_t e = hipMalloc(&tmp, bytes);
+    if (e != hipSuccess || !tmp) {
+        (void)hipGetLastError();
+        return fail(MERF_E_OOM, "hipMalloc of %zu scratch bytes failed", bytes);
+    }
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    uint8_t *seed = static_cast<uint8_t *>(tmp);
+    int32_t *sat = reinterpret_cast<int32_t *>(seed + align_up(n, 256));
+    e = launch_octant_extents(lv, seed, sat, out_dev, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return hip_fail(e, "octant extent grid");
     return MERF_OK;
 }
 

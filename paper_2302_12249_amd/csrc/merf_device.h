@@ -20,6 +20,7 @@ constexpr int kMlpParams = kMlpIn * kMlpHidden + kMlpHidden + kMlpHidden * kMlpH
 constexpr int kTile = 8;                         // a wave renders an 8x8 pixel tile
 constexpr int kCamsPerLaunch = 16;               // cameras carried in one launch's arguments
 constexpr int kMaxDistRes = 1024;                // finest occupancy resolution (distance grid)
+constexpr int kOctMaxRes = 256;                  // up to this r_f the grid has eight octant forms
 
 // Scene as laid out in device memory.
 //   brick_index  int32 [(L/8)^3] z-major: brick slot; blocks whose brick would
@@ -30,11 +31,15 @@ constexpr int kMaxDistRes = 1024;                // finest occupancy resolution 
 //   planes       uint8 [3][R][R][8]: P_x[z][y], P_y[z][x], P_z[y][x].
 //   occ[l]       uint8 [r^3] z-major, coarse to fine; each resolution divides
 //                the next finer one.
-//   dist         uint8 [r_f^3] z-major at the finest resolution r_f: Chebyshev
-//                distance, in cells, from the cell to the nearest cell whose
-//                every level is occupied (0 = the cell is occupied at every
-//                level; capped at 255).  Cells within distance D - 1 of a
-//                cell with value D are all empty.
+//   dist         empty-space grid at the finest resolution r_f, z-major; 0
+//                marks a cell occupied at every level.  Either (r_f <= 256)
+//                eight octant grids uint8 [8][r_f^3]: octant o (bit 0: -x,
+//                bit 1: -y, bit 2: -z) holds E, the largest cube of E cells
+//                a side with a corner at the cell, extending in the
+//                octant's directions, that is empty (capped at 255); or one
+//                grid uint8 [r_f^3] of the Chebyshev distance D to the
+//                nearest occupied cell, shared by all octants
+//                (dist_oct_stride = 0): the same forward cube with E = D.
 //   mlp          float32 W0[34][16] b0 W1[16][16] b1 W2[16][3] b2.
 // A scene without a grid carries a stand-in grid (L = 8, one index entry
 // pointing at the zero brick); a scene without planes carries all-zero 2x2
@@ -52,6 +57,7 @@ struct DevScene {
     float occ_cell[kMaxLevels];                  // cell edge 4 / r of each level
     int32_t dist_res;                            // r_f
     float dist_cell;                             // 4 / r_f
+    uint32_t dist_oct_stride;                    // bytes between octant grids (0: one shared grid)
     float m_density, m_feature;
     float nsrc;                                  // present sources: grid 1 + planes 3
     int32_t res;                                 // finest present resolution max(L, R) of the scene
@@ -103,5 +109,8 @@ struct OccLevels {
 };
 hipError_t launch_distance_grid(const OccLevels &lv, uint8_t *tmp0, uint8_t *tmp1, uint8_t *dist,
                                 hipStream_t stream);
+// Forward empty extents of DevScene::dist in its eight-octant form (seed:
+// scratch of r_f^3 bytes; sat: scratch of r_f^3 int32; out: 8 r_f^3 bytes).
+hipError_t launch_octant_extents(const OccLevels &lv, uint8_t *seed, int32_t *sat, uint8_t *out, hipStream_t stream);
 
 }  // namespace merf

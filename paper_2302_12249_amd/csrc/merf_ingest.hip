@@ -102,7 +102,87 @@ __global__ void k_dist_axis(const uint8_t *__restrict__ in, uint8_t *__restrict_
     }
 }
 
+// Forward empty extents, step 1: inclusive prefix sums of the occupancy
+// (seed 0 = occupied) along x, then y, then z -- one thread per line.
+__global__ void k_occ_prefix_x(const uint8_t *__restrict__ seed, int32_t *__restrict__ sat, int r) {
+    const int64_t line = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (line >= (int64_t)r * r) return;
+    int32_t acc = 0;
+    for (int x = 0; x < r; ++x) {
+        acc += seed[line * r + x] == 0 ? 1 : 0;
+        sat[line * r + x] = acc;
+    }
+}
+
+__global__ void k_prefix_axis(int32_t *__restrict__ sat, int r, int axis) {
+    const int64_t line = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (line >= (int64_t)r * r) return;
+    const int64_t base = axis == 1 ? (line / r) * r * r + line % r : line;   // y: (z, x) lines; z: (y, x)
+    const int64_t stride = axis == 1 ? (int64_t)r : (int64_t)r * r;
+    int32_t acc = 0;
+    for (int i = 0; i < r; ++i) {
+        acc += sat[base + i * stride];
+        sat[base + i * stride] = acc;
+    }
+}
+
+__device__ __forceinline__ int32_t sat_at(const int32_t *sat, int r, int x, int y, int z) {
+    return (x < 0 || y < 0 || z < 0) ? 0 : sat[((int64_t)z * r + y) * r + x];
+}
+
+// Occupied cells in the box [x0, x1] x [y0, y1] x [z0, z1] (inclusive).
+__device__ __forceinline__ int32_t box_count(const int32_t *sat, int r, int x0, int y0, int z0, int x1, int y1,
+                                             int z1) {
+    return sat_at(sat, r, x1, y1, z1) - sat_at(sat, r, x0 - 1, y1, z1) - sat_at(sat, r, x1, y0 - 1, z1) -
+           sat_at(sat, r, x1, y1, z0 - 1) + sat_at(sat, r, x0 - 1, y0 - 1, z1) + sat_at(sat, r, x0 - 1, y1, z0 - 1) +
+           sat_at(sat, r, x1, y0 - 1, z0 - 1) - sat_at(sat, r, x0 - 1, y0 - 1, z0 - 1);
+}
+
+// Step 2: for each cell and each octant o (bit 0: -x, bit 1: -y, bit 2: -z)
+// the largest k <= 255 such that the cube of k cells on a side with a corner
+// at the cell and extending in the octant's directions holds no occupied
+// cell (cells outside the grid are empty); 0 for an occupied cell.  Found by
+// bisection, since the count only grows with k.
+__global__ void k_octant_extent(const int32_t *__restrict__ sat, int r, uint8_t *__restrict__ out) {
+    const int64_t n = (int64_t)r * r * r;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= 8 * n) return;
+    const int o = (int)(gid / n);
+    const int64_t cell = gid % n;
+    const int x = (int)(cell % r), y = (int)((cell / r) % r), z = (int)(cell / ((int64_t)r * r));
+    if (box_count(sat, r, x, y, z, x, y, z) != 0) {
+        out[gid] = 0;
+        return;
+    }
+    auto empty = [&](int k) {
+        const int x0 = (o & 1) ? max(x - k + 1, 0) : x, x1 = (o & 1) ? x : min(x + k - 1, r - 1);
+        const int y0 = (o & 2) ? max(y - k + 1, 0) : y, y1 = (o & 2) ? y : min(y + k - 1, r - 1);
+        const int z0 = (o & 4) ? max(z - k + 1, 0) : z, z1 = (o & 4) ? z : min(z + k - 1, r - 1);
+        return box_count(sat, r, x0, y0, z0, x1, y1, z1) == 0;
+    };
+    int lo = 1, hi = 255;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (empty(mid)) lo = mid;
+        else hi = mid - 1;
+    }
+    out[gid] = (uint8_t)lo;
+}
+
 }  // namespace
+
+hipError_t launch_octant_extents(const OccLevels &lv, uint8_t *seed, int32_t *sat, uint8_t *out, hipStream_t stream) {
+    const int r = lv.res[lv.n - 1];
+    const int64_t n = (int64_t)r * r * r;
+    if (n <= 0 || r > kMaxDistRes) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_occ_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, lv, seed);
+    const unsigned lines = (unsigned)(((int64_t)r * r + 255) / 256);
+    hipLaunchKernelGGL(k_occ_prefix_x, dim3(lines), dim3(256), 0, stream, seed, sat, r);
+    hipLaunchKernelGGL(k_prefix_axis, dim3(lines), dim3(256), 0, stream, sat, r, 1);
+    hipLaunchKernelGGL(k_prefix_axis, dim3(lines), dim3(256), 0, stream, sat, r, 2);
+    hipLaunchKernelGGL(k_octant_extent, dim3((unsigned)((8 * n + 255) / 256)), dim3(256), 0, stream, sat, r, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_pack_bricks(const uint8_t *blocks, const int32_t *block_index, const int32_t *brick_pos,
                               int nbricks, int L, uint8_t *bricks, hipStream_t stream) {

@@ -393,6 +393,7 @@ struct Segment {
     float len, iex, iey, iez;       // length; inverse direction (+-inf where e = +-0)
     float tb;                       // world parameter of the end (kInf: last)
     int n, k, reg, reg_next;        // interval count, next interval, regions
+    uint32_t doff;                  // byte offset of the empty-space grid of this direction's octant
 };
 
 // Contracted end point of the segment of region reg that ends at world
@@ -404,7 +405,8 @@ __device__ __forceinline__ float3 segment_end(float3 o, float3 d, float tb, int 
 
 // Set up the segment of the ray that starts at world parameter ta in region
 // reg: find where the region next changes (Eq. 7 breakpoints), map both ends.
-__device__ __forceinline__ void open_segment(float3 o, float3 d, float ta, int reg, float istep, Segment &s) {
+__device__ __forceinline__ void open_segment(float3 o, float3 d, float ta, int reg, float istep, uint32_t oct_stride,
+                                             Segment &s) {
     const Candidates C = make_candidates(o, d);
     float tb = kInf, cur = ta;
     int reg_next = reg;
@@ -442,6 +444,7 @@ __device__ __forceinline__ void open_segment(float3 o, float3 d, float ta, int r
     s.iex = rcp(e.x);
     s.iey = rcp(e.y);
     s.iez = rcp(e.z);
+    s.doff = oct_stride * (uint32_t)((s.iex < 0.0f ? 1 : 0) | (s.iey < 0.0f ? 2 : 0) | (s.iez < 0.0f ? 4 : 0));
 }
 
 // Deferred MLP (Eq. 3, App. B) for the 64 pixels of a wave on the matrix
@@ -634,7 +637,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     {
         const Candidates C = make_candidates(o, d);
         const float c1 = next_candidate(C, 0.0f);
-        open_segment(o, d, 0.0f, region_at(o, d, c1 < kInf ? 0.5f * c1 : 1.0f), istep, s);
+        open_segment(o, d, 0.0f, region_at(o, d, c1 < kInf ? 0.5f * c1 : 1.0f), istep, sc.dist_oct_stride, s);
     }
     int nseg = 1;
     bool alive = active, terminated = false;
@@ -670,7 +673,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
                         alive = false;
                         break;
                     }
-                    open_segment(o, d, s.tb, s.reg_next, istep, s);
+                    open_segment(o, d, s.tb, s.reg_next, istep, sc.dist_oct_stride, s);
                     ++nseg;
                     known[0] = known[1] = known[2] = known[3] = 0.0f;
                     continue;
@@ -687,10 +690,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
                 int empty = -1;
                 float uexit = 0.0f;
                 if constexpr (!kLevels) {
-                    // distance grid: a cell at Chebyshev distance D > 0 from the
-                    // nearest occupied cell is the centre of an empty cube of
-                    // 2D - 1 cells; leave the whole cube (D = 0: occupied, the
-                    // cube is the cell itself)
+                    // empty-space grid of the segment's octant: a value D > 0
+                    // means the cube of D cells a side with a corner at this
+                    // cell, extending in the segment's directions, is empty;
+                    // leave the whole cube (D = 0: occupied, the cube is the
+                    // cell itself)
                     if (!(um < known[0])) {
                         const int r = sc.dist_res;
                         // cell of p: (p + 2) r / 4 rounded down; contracted
@@ -701,7 +705,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
                         const int qy = min((int)fmaf(p.y, os, os2), r - 1);
                         const int qz = min((int)fmaf(p.z, os, os2), r - 1);
                         if (kStats) ++cnt.occ_lookups;
-                        const int D = load_at<uint8_t>(sc.dist, cell_offset(qx, qy, qz, r));
+                        const int D = load_at<uint8_t>(sc.dist, s.doff + cell_offset(qx, qy, qz, r));
                         const int ext = D > 0 ? D - 1 : 0;
                         const float h = sc.dist_cell;
                         const float bx = (float)(s.iex > 0.0f ? qx + ext + 1 : qx - ext) * h - 2.0f;

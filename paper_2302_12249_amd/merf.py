@@ -54,7 +54,7 @@ class merf_render_params(C.Structure):
 
 EXPORTS = ["merf_scene_upload", "merf_render", "merf_free", "merf_last_error", "merf_set_hbm_budget",
            "merf_hbm_in_use", "merf_scene_bytes", "merf_dequantize", "merf_occupancy_pyramid",
-           "merf_distance_grid"]
+           "merf_distance_grid", "merf_octant_extent_grid"]
 
 _lib = None
 
@@ -90,6 +90,8 @@ def load(path: str = LIB_PATH):
     lib.merf_distance_grid.argtypes = [C.POINTER(C.c_void_p), C.POINTER(C.c_int32), C.c_int32, C.c_void_p,
                                        C.c_void_p]
     lib.merf_distance_grid.restype = C.c_int
+    lib.merf_octant_extent_grid.argtypes = lib.merf_distance_grid.argtypes
+    lib.merf_octant_extent_grid.restype = C.c_int
     _lib = lib
     return lib
 
@@ -219,19 +221,22 @@ def occupancy_pyramid(mask, factors, stream=None):
     return outs
 
 
-def distance_grid(levels, stream=None):
-    """Empty-space distance grid of an occupancy hierarchy (merf_distance_grid).
-    levels: torch uint8 cubes [r_l, r_l, r_l] on the GPU, coarse to fine; returns
-    a torch uint8 [r, r, r] for the finest r."""
+def distance_grid(levels, stream=None, octants=False):
+    """Empty-space grid of an occupancy hierarchy: the Chebyshev distance grid
+    (merf_distance_grid; torch uint8 [r, r, r]) or, with octants=True, the
+    eight forward-extent grids (merf_octant_extent_grid; [8, r, r, r]).
+    levels: torch uint8 cubes [r_l, r_l, r_l] on the GPU, coarse to fine."""
     import torch
     for o in levels:
         assert o.is_cuda and o.dtype == torch.uint8 and o.is_contiguous() and o.dim() == 3
     r = int(levels[-1].shape[0])
-    out = torch.empty((r, r, r), dtype=torch.uint8, device=levels[-1].device)
+    shape = (8, r, r, r) if octants else (r, r, r)
+    out = torch.empty(shape, dtype=torch.uint8, device=levels[-1].device)
     ptrs = (C.c_void_p * len(levels))(*[o.data_ptr() for o in levels])
     res = (C.c_int32 * len(levels))(*[int(o.shape[0]) for o in levels])
     st = stream if stream is not None else torch.cuda.current_stream()
-    _check(load().merf_distance_grid(ptrs, res, len(levels), C.c_void_p(out.data_ptr()), C.c_void_p(st.cuda_stream)))
+    fn = load().merf_octant_extent_grid if octants else load().merf_distance_grid
+    _check(fn(ptrs, res, len(levels), C.c_void_p(out.data_ptr()), C.c_void_p(st.cuda_stream)))
     return out
 
 

@@ -193,6 +193,9 @@ def test_distance_grid_argument_checks():
     res = (C.c_int32 * 2)(8, 16)
     assert lib.merf_distance_grid(ptrs, res, 0, C.c_void_p(16), None) == merf.MERF_E_INVALID
     assert lib.merf_distance_grid(ptrs, res, 2, None, None) == merf.MERF_E_INVALID
+    for fn in (lib.merf_distance_grid, lib.merf_octant_extent_grid):
+        assert fn(ptrs, (C.c_int32 * 2)(6, 16), 2, C.c_void_p(16), None) == merf.MERF_E_INVALID
+        assert fn(ptrs, res, 5, C.c_void_p(16), None) == merf.MERF_E_INVALID
 
 
 def test_representation_variants_validate():

@@ -98,3 +98,52 @@ def test_distance_grid_matches_definition(torch, merf, case):
     torch.cuda.synchronize()
     got = got.cpu().numpy()
     assert np.array_equal(got, want), np.argwhere(got != want)[:5]
+
+
+def octant_brute(levels):
+    """Octant extents by definition: for each finest cell and octant o (bit 0:
+    -x, bit 1: -y, bit 2: -z), the largest k <= 255 such that the k-cell cube
+    with a corner at the cell, extending in o's directions and clipped to the
+    grid, has no cell occupied at every level; 0 for such a cell."""
+    rf = levels[-1].shape[0]
+    comb = np.ones((rf,) * 3, bool)
+    for o in levels:
+        k = rf // o.shape[0]
+        comb &= np.repeat(np.repeat(np.repeat(o > 0, k, 0), k, 1), k, 2)
+    out = np.zeros((8, rf, rf, rf), np.uint8)
+    for o in range(8):
+        for z in range(rf):
+            for y in range(rf):
+                for x in range(rf):
+                    if comb[z, y, x]:
+                        continue
+                    k = 1
+                    while k < 255:
+                        lo = [c - k if (o >> a) & 1 else c for a, c in enumerate((x, y, z))]
+                        hi = [c + 1 if (o >> a) & 1 else c + k + 1 for a, c in enumerate((x, y, z))]
+                        sl = comb[max(lo[2], 0):min(hi[2], rf), max(lo[1], 0):min(hi[1], rf),
+                                  max(lo[0], 0):min(hi[0], rf)]
+                        if sl.any():
+                            break
+                        k += 1
+                    out[o, z, y, x] = k
+    return out
+
+
+@pytest.mark.parametrize("case", ["pyramid", "and_of_levels", "empty"])
+def test_octant_extent_grid_matches_definition(torch, merf, case):
+    print(f"octant extent grid: {case}", flush=True)
+    rng = np.random.default_rng(11)
+    if case == "pyramid":
+        fine = (rng.random((16, 16, 16)) < 0.01).astype(np.uint8)
+        levels = [synth.maxpool(fine, 4), synth.maxpool(fine, 2), fine]
+    elif case == "and_of_levels":
+        fine = (rng.random((12, 12, 12)) < 0.05).astype(np.uint8)
+        levels = [(rng.random((3, 3, 3)) < 0.6).astype(np.uint8), fine]
+    else:
+        levels = [np.zeros((2, 2, 2), np.uint8), np.zeros((8, 8, 8), np.uint8)]
+    want = octant_brute(levels)
+    got = merf.distance_grid([torch.from_numpy(np.ascontiguousarray(o)).cuda() for o in levels], octants=True)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    assert np.array_equal(got, want), np.argwhere(got != want)[:5]
