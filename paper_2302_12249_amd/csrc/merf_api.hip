@@ -396,6 +396,19 @@ int merf_scene_upload(const merf_scene_desc *desc, merf_scene_t *out) {
     ds.occ_levels = desc->occ_levels;
     ds.m_density = desc->m_density;
     ds.m_feature = desc->m_feature;
+    // kernel constants (after every field they derive from)
+    ds.p_scale = (float)ds.R * 0.25f;
+    ds.p_off = 2.0f * ds.p_scale - 0.5f;
+    ds.p_max = (float)(ds.R - 1);
+    ds.g_scale = (float)ds.L * 0.25f;
+    ds.g_off = 2.0f * ds.g_scale - 0.5f;
+    ds.g_max = (float)(ds.L - 1);
+    ds.d_scale = ds.m_density * (2.0f / 255.0f);
+    ds.d_off = -ds.nsrc * ds.m_density;
+    ds.f_scale = ds.m_feature * (2.0f / 255.0f);
+    ds.f_off = -ds.nsrc * ds.m_feature;
+    ds.dist_scale = (float)ds.dist_res * 0.25f;
+    ds.dist_off = 2.0f * ds.dist_scale;
     {
         std::lock_guard<std::mutex> lk(g_mutex);
         g_live.insert(s);

@@ -61,6 +61,14 @@ struct DevScene {
     float m_density, m_feature;
     float nsrc;                                  // present sources: grid 1 + planes 3
     int32_t res;                                 // finest present resolution max(L, R) of the scene
+    // constants of the kernels, computed once on the host in float32 exactly
+    // as the kernels would (uniform values the compiler would otherwise hold
+    // in vector registers):
+    float p_scale, p_off, p_max;                 // plane texel coordinate fma(p, R/4, R/2 - 1/2), max R - 1
+    float g_scale, g_off, g_max;                 // grid voxel coordinate, the same with L
+    float d_scale, d_off;                        // density: 2 m_d / 255 and -nsrc m_d
+    float f_scale, f_off;                        // appearance: 2 m_f / 255 and -nsrc m_f
+    float dist_scale, dist_off;                  // empty-space cell: fma(p, r_f/4, r_f/2)
 };
 
 struct DevCamera {

@@ -213,7 +213,7 @@ struct Footprint {
 __device__ __forceinline__ Footprint footprint(const DevScene &sc, float3 p) {
     Footprint f;
     // ---- three planes, bilinear: P_x(y, z), P_y(x, z), P_z(x, y)
-    const float ps = (float)sc.R * 0.25f, ps2 = 2.0f * ps - 0.5f, pmax = (float)(sc.R - 1);
+    const float ps = sc.p_scale, ps2 = sc.p_off, pmax = sc.p_max;
     float hx = __builtin_amdgcn_fmed3f(fmaf(p.x, ps, ps2), 0.0f, pmax);
     float hy = __builtin_amdgcn_fmed3f(fmaf(p.y, ps, ps2), 0.0f, pmax);
     float hz = __builtin_amdgcn_fmed3f(fmaf(p.z, ps, ps2), 0.0f, pmax);
@@ -225,7 +225,7 @@ __device__ __forceinline__ Footprint footprint(const DevScene &sc, float3 p) {
     f.op[1] = plane + (uint32_t)jz * row + (uint32_t)jx * kChannels;
     f.op[2] = 2u * plane + (uint32_t)jy * row + (uint32_t)jx * kChannels;
     // ---- sparse 3D grid, trilinear inside one apron brick
-    const float gs = (float)sc.L * 0.25f, gs2 = 2.0f * gs - 0.5f, gmax = (float)(sc.L - 1);
+    const float gs = sc.g_scale, gs2 = sc.g_off, gmax = sc.g_max;
     float gx = __builtin_amdgcn_fmed3f(fmaf(p.x, gs, gs2), 0.0f, gmax);
     float gy = __builtin_amdgcn_fmed3f(fmaf(p.y, gs, gs2), 0.0f, gmax);
     float gz = __builtin_amdgcn_fmed3f(fmaf(p.z, gs, gs2), 0.0f, gmax);
@@ -306,8 +306,6 @@ __device__ __forceinline__ SampleResult eval_sample(const DevScene &sc, float3 p
             lo[2 * i + 1] = x.g[i].z; hi[2 * i + 1] = x.g[i].w; w[2 * i + 1] = f.fx * wyz[i];
         }
     }
-    // number of sources whose weights sum to one
-    const float nsrc = sc.nsrc;
     // ---- Eq. 8 dequantises each code affinely, q(b) = a b - m with a = 2m/255,
     // and the weights of each present source sum to one, so
     // sum_i w_i q(b_i) = a * sum_i w_i b_i - n m exactly (n sources: 4 for
@@ -318,17 +316,17 @@ __device__ __forceinline__ SampleResult eval_sample(const DevScene &sc, float3 p
     // (below 1e-6 relative).  The FP16 path dequantises every code to its
     // correctly rounded float16 value first (deq_f16) and interpolates those
     // values with FP32 weights and FP32 sums.
+    // (a = d_scale or f_scale, n m = -d_off or -f_off, precomputed)
     const float md = sc.m_density, mf = sc.m_feature;
     // ---- density first (Sec. 6): appearance is read only when alpha != 0
     float s0 = 0.0f;
     if constexpr (kFeatF16) {
-        const float ad = md * (2.0f / 255.0f);
 #pragma unroll
-        for (int i = 0; i < 20; ++i) s0 = fmaf(w[i], deq_f16(byte_of(lo[i], 0), ad, md), s0);
+        for (int i = 0; i < 20; ++i) s0 = fmaf(w[i], deq_f16(byte_of(lo[i], 0), sc.d_scale, md), s0);
     } else {
 #pragma unroll
         for (int i = 0; i < 20; ++i) s0 = fmaf(w[i], (float)byte_of(lo[i], 0), s0);
-        s0 = fmaf(s0, md * (2.0f / 255.0f), -nsrc * md);
+        s0 = fmaf(s0, sc.d_scale, sc.d_off);
     }
     SampleResult r;
     float tau = __expf(s0);                       // Eq. 6
@@ -337,7 +335,7 @@ __device__ __forceinline__ SampleResult eval_sample(const DevScene &sc, float3 p
         float sa[7];
 #pragma unroll
         for (int c = 0; c < 7; ++c) sa[c] = 0.0f;
-        const float af = mf * (2.0f / 255.0f);
+        const float af = sc.f_scale;
         if constexpr (kFeatF16) {
 #pragma unroll
             for (int i = 0; i < 20; ++i) {
@@ -355,7 +353,7 @@ __device__ __forceinline__ SampleResult eval_sample(const DevScene &sc, float3 p
                 for (int c = 0; c < 4; ++c) sa[3 + c] = fmaf(w[i], (float)byte_of(hi[i], c), sa[3 + c]);
             }
 #pragma unroll
-            for (int c = 0; c < 7; ++c) sa[c] = fmaf(sa[c], af, -nsrc * mf);
+            for (int c = 0; c < 7; ++c) sa[c] = fmaf(sa[c], af, sc.f_off);
         }
 #pragma unroll
         for (int c = 0; c < 7; ++c) r.sg[c] = sigmoid(sa[c]);
@@ -700,7 +698,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
                         // cell of p: (p + 2) r / 4 rounded down; contracted
                         // points have p >= -2 up to rounding, so truncation
                         // equals the floor and no lower clamp is needed
-                        const float os = (float)r * 0.25f, os2 = 2.0f * os;
+                        const float os = sc.dist_scale, os2 = sc.dist_off;
                         const int qx = min((int)fmaf(p.x, os, os2), r - 1);
                         const int qy = min((int)fmaf(p.y, os, os2), r - 1);
                         const int qz = min((int)fmaf(p.z, os, os2), r - 1);
@@ -849,8 +847,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 
     const float3 h = deferred_mlp_mfma<kMlpPrec>(sc.mlp, lds, acc, d);
     if (active) {
+        // the pixel again from the lane id (an opaque copy, so the compiler
+        // recomputes it instead of holding px and py through the march)
+        int l2 = lane;
+        asm volatile("" : "+v"(l2));
+        const int ox = (lt % cam.tiles_x) * kTile + (l2 & (kTile - 1));
+        const int oy = (lt / cam.tiles_x) * kTile + (l2 / kTile);
         float4 rgba = make_float4(acc.cd0 + h.x, acc.cd1 + h.y, acc.cd2 + h.z, 1.0f - acc.T);
-        *reinterpret_cast<float4 *>(cam.out + ((int64_t)py * cam.width + px) * 4) = rgba;
+        *reinterpret_cast<float4 *>(cam.out + ((int64_t)oy * cam.width + ox) * 4) = rgba;
     }
     if (kStats && rb.rec_count) rb.rec_count[tile * 64 + lane] = (int32_t)cnt.evaluated;
     if (kStats) {
