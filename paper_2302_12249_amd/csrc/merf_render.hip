@@ -406,10 +406,20 @@ __device__ __forceinline__ float3 segment_end(float3 o, float3 d, float tb, int 
 __device__ __forceinline__ void open_segment(float3 o, float3 d, float ta, int reg, float istep, uint32_t oct_stride,
                                              Segment &s) {
     const Candidates C = make_candidates(o, d);
+    // The region can change only where it is decided: inside the cube when
+    // some |x_j| crosses 1 (candidates 0..5); in the outer region of axis a
+    // when |x_a| crosses 1 or another |x_k| meets |x_a| (candidates 2a, 2a+1
+    // and the pairs with a).  The others are skipped; the next region is
+    // still sampled between consecutive candidates of the full set.
+    const int ax = (reg - 1) >> 1;
+    const uint32_t relevant = reg == 0 ? 0x03Fu : (ax == 0 ? 0x3C3u : (ax == 1 ? 0xCCCu : 0xF30u));
+    Candidates Cr;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) Cr.c[i] = (relevant >> i) & 1u ? C.c[i] : kInf;
     float tb = kInf, cur = ta;
     int reg_next = reg;
     for (int it = 0; it < 13; ++it) {
-        float n1 = next_candidate(C, cur);
+        float n1 = next_candidate(Cr, cur);
         if (!(n1 < kInf)) break;
         float n2 = next_candidate(C, n1);
         float tm = n2 < kInf ? 0.5f * (n1 + n2) : 2.0f * n1 + 1.0f;
