@@ -170,14 +170,20 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? l
 
 __device__ __forceinline__ float sigmoid(float x) { return __builtin_amdgcn_rcpf(1.0f + __expf(-x)); }
 
-// XCD-aware tile order: consecutive workgroups are dispatched round-robin over
-// the 8 XCDs, so give each XCD a contiguous run of tiles (neighbouring tiles
-// gather neighbouring texels and share that XCD's L2).
+// XCD-aware tile order.  Consecutive workgroups are dispatched round-robin
+// over the 8 XCDs (workgroup b runs on XCD b % 8 as that XCD's (b / 8)-th),
+// with no balancing between XCDs.  Each XCD therefore gets runs of
+// kXcdChunk consecutive tiles (neighbouring tiles gather neighbouring texels
+// and share that XCD's L2), and the runs are dealt to the XCDs in turn over
+// the whole launch, so every XCD gets a similar share of the image's work.
+// Workgroups past the last whole round of runs keep their own tile.
+constexpr int kXcdChunk = 4;
 __device__ __forceinline__ int xcd_remap(int bid, int n) {
-    const int nx = 8;
-    int q = n / nx, r = n % nx;
-    int x = bid % nx, i = bid / nx;
-    return x * q + min(x, r) + i;
+    constexpr int nx = 8;
+    const int full = n / (nx * kXcdChunk) * (nx * kXcdChunk);
+    if (bid >= full) return bid;
+    const int x = bid % nx, i = bid / nx;
+    return ((i / kXcdChunk) * nx + x) * kXcdChunk + i % kXcdChunk;
 }
 
 struct Accum {
