@@ -533,6 +533,27 @@ __device__ __forceinline__ float3 deferred_mlp_mfma(const float *__restrict__ W,
     const int lane = (int)threadIdx.x, j = lane & 15, g = lane >> 4;
     const float *W0 = W, *b0 = W0 + kMlpIn * kMlpHidden, *W1 = b0 + kMlpHidden, *b1 = W1 + kMlpHidden * kMlpHidden,
                 *W2 = b1 + kMlpHidden, *b2 = W2 + kMlpHidden * kMlpOut;
+    // Weights and biases first, so their loads overlap the input encoding.
+    // Layer-1 A operand W0^T[hidden j][k]: fp32 steps take k = 9g + q,
+    // half-precision steps k = 16 (q / 4) + 4g + q % 4; rows past the 34
+    // inputs and output columns past 3 are zero (loaded from a valid address,
+    // then replaced, so no load is conditional).
+    constexpr int kA0 = kPrec == 0 ? 9 : 12;
+    float a0[kA0], a1[4], a2[4], c0[4], c1[4];
+#pragma unroll
+    for (int q = 0; q < kA0; ++q) {
+        const int k = kPrec == 0 ? 9 * g + q : 16 * (q >> 2) + 4 * g + (q & 3);
+        const float v = W0[min(k, kMlpIn - 1) * kMlpHidden + j];
+        a0[q] = k < kMlpIn ? v : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        a1[q] = W1[(4 * g + q) * kMlpHidden + j];
+        const float v = W2[(4 * g + q) * kMlpOut + min(j, kMlpOut - 1)];
+        a2[q] = j < kMlpOut ? v : 0.0f;
+        c0[q] = b0[4 * g + q];
+        c1[q] = b1[4 * g + q];
+    }
     {
         float x[48];
         mlp_encode(x, acc, d);
@@ -546,64 +567,70 @@ __device__ __forceinline__ float3 deferred_mlp_mfma(const float *__restrict__ W,
             for (int i = 0; i < Lds::kWidth / 4; ++i) row[i] = to_half4<kPrec>(x + 4 * i);
         }
     }
-    // layer-1 A operand W0^T[hidden j][k]: fp32 steps take k = 9g + q,
-    // half-precision steps k = 16 (q / 4) + 4g + q % 4 (zero past 34)
-    constexpr int kA0 = kPrec == 0 ? 9 : 12;
-    float a0[kA0], a1[4], a2[4];
-#pragma unroll
-    for (int q = 0; q < kA0; ++q) {
-        const int k = kPrec == 0 ? 9 * g + q : 16 * (q >> 2) + 4 * g + (q & 3);
-        a0[q] = k < kMlpIn ? W0[k * kMlpHidden + j] : 0.0f;
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        a1[q] = W1[(4 * g + q) * kMlpHidden + j];
-        a2[q] = j < kMlpOut ? W2[(4 * g + q) * kMlpOut + j] : 0.0f;
-    }
     __syncthreads();
-    floatx4 y[4];
-    // one block of 16 pixels at a time through all three layers
+    // the four blocks of 16 pixels go through each layer together, so four
+    // independent accumulation chains keep the matrix core busy
+    floatx4 c[4];
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-        floatx4 c = {0.0f, 0.0f, 0.0f, 0.0f};
-        if constexpr (kPrec == 0) {
-            const float *xr = xs + (16 * mt + j) * Lds::kStride;
+    for (int mt = 0; mt < 4; ++mt) c[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    if constexpr (kPrec == 0) {
 #pragma unroll
-            for (int q = 0; q < 9; ++q) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[q], xr[9 * g + q], c, 0, 0, 0);
-        } else {
-            const half_t<kPrec> *xr = reinterpret_cast<const half_t<kPrec> *>(xs) + (16 * mt + j) * Lds::kStride;
+        for (int q = 0; q < 9; ++q)
 #pragma unroll
-            for (int ks = 0; ks < 3; ++ks)
-                c = mfma16<kPrec>(to_half4<kPrec>(a0 + 4 * ks),
-                                  *reinterpret_cast<const half4_t<kPrec> *>(xr + 16 * ks + 4 * g), c);
+            for (int mt = 0; mt < 4; ++mt)
+                c[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[q], xs[(16 * mt + j) * Lds::kStride + 9 * g + q], c[mt],
+                                                             0, 0, 0);
+    } else {
+#pragma unroll
+        for (int ks = 0; ks < 3; ++ks) {
+            const half4_t<kPrec> a = to_half4<kPrec>(a0 + 4 * ks);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const half_t<kPrec> *xr = reinterpret_cast<const half_t<kPrec> *>(xs) + (16 * mt + j) * Lds::kStride;
+                c[mt] = mfma16<kPrec>(a, *reinterpret_cast<const half4_t<kPrec> *>(xr + 16 * ks + 4 * g), c[mt]);
+            }
         }
-        float h[4];
+    }
+    float h[4][4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) h[r] = fmaxf(c[r] + b0[4 * g + r], 0.0f);
-        c = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-        if constexpr (kPrec == 0) {
+    for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[q], h[q], c, 0, 0, 0);
-        } else {
-            c = mfma16<kPrec>(to_half4<kPrec>(a1), to_half4<kPrec>(h), c);
-        }
+        for (int r = 0; r < 4; ++r) h[mt][r] = fmaxf(c[mt][r] + c0[r], 0.0f);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) h[r] = fmaxf(c[r] + b1[4 * g + r], 0.0f);
-        c = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-        if constexpr (kPrec == 0) {
+    for (int mt = 0; mt < 4; ++mt) c[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    if constexpr (kPrec == 0) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[q], h[q], c, 0, 0, 0);
-        } else {
-            c = mfma16<kPrec>(to_half4<kPrec>(a2), to_half4<kPrec>(h), c);
-        }
-        y[mt] = c;
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) c[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[q], h[mt][q], c[mt], 0, 0, 0);
+    } else {
+        const half4_t<kPrec> a = to_half4<kPrec>(a1);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) c[mt] = mfma16<kPrec>(a, to_half4<kPrec>(h[mt]), c[mt]);
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) h[mt][r] = fmaxf(c[mt][r] + c1[r], 0.0f);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) c[mt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    if constexpr (kPrec == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) c[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[q], h[mt][q], c[mt], 0, 0, 0);
+    } else {
+        const half4_t<kPrec> a = to_half4<kPrec>(a2);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) c[mt] = mfma16<kPrec>(a, to_half4<kPrec>(h[mt]), c[mt]);
     }
     __syncthreads();   // every lane has read its inputs; reuse xs for the outputs
+    // output unit r of pixel 16 mt + j is c[mt][r] of lane j (g = 0)
     if (g == 0) {
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-            for (int r = 0; r < kMlpOut; ++r) xs[(16 * mt + j) * Lds::kOut + r] = y[mt][r] + b2[r];
+            for (int r = 0; r < kMlpOut; ++r) xs[(16 * mt + j) * Lds::kOut + r] = c[mt][r] + b2[r];
     }
     __syncthreads();
     return make_float3(xs[lane * Lds::kOut + 0], xs[lane * Lds::kOut + 1], xs[lane * Lds::kOut + 2]);
