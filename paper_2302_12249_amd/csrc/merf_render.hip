@@ -637,12 +637,13 @@ __device__ __forceinline__ float3 deferred_mlp_mfma(const float *__restrict__ W,
 }
 
 // Samples a lane may park ahead of its compositing, and the LDS of a wave:
-// the parking area (kQueue x 64 x (p, delta), kQueue x 64 x 8 results, the
-// 64-entry shading map) during the march, the MLP staging afterwards.
+// during the march the parking area (kQueue x 64 x (p, delta)), the results
+// of one shading pass (64 x 8 floats, by shading slot) and the 64-entry
+// shading map; the MLP staging afterwards.
 constexpr int kQueue = 3;
+constexpr int kParkFloats = 4 * 64 * kQueue + 8 * 64 + 64;
 template <int kPrec>
-constexpr int kLdsFloats = MlpLds<kPrec>::kFloats > 12 * 64 * kQueue + 64 ? MlpLds<kPrec>::kFloats
-                                                                          : 12 * 64 * kQueue + 64;
+constexpr int kLdsFloats = MlpLds<kPrec>::kFloats > kParkFloats ? MlpLds<kPrec>::kFloats : kParkFloats;
 
 // kLevels: empty space is skipped with the occupancy levels themselves
 // (skip_mode 1) instead of the distance grid (skip_mode 0).
@@ -693,8 +694,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     // termination are dropped, so the image is the one a one-sample-at-a-time
     // march gives.
     float4 *pq = reinterpret_cast<float4 *>(lds);             // [kQueue][64] parked (p, delta)
-    float4 *rs = pq + kQueue * 64;                            // [kQueue][64] x 2: shaded results
-    int *imap = reinterpret_cast<int *>(rs + 2 * kQueue * 64); // [64] shading slot -> parked entry
+    float4 *rs = pq + kQueue * 64;                            // [64] x 2: results by shading slot
+    int *imap = reinterpret_cast<int *>(rs + 2 * 64);          // [64] shading slot -> parked entry
     int pc = 0;                                               // samples parked by this lane
     while (__any(alive || pc > 0)) {
         // ---- march: live lanes park up to kQueue samples, one step per
@@ -843,8 +844,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
             const int e = imap[lane];
             const float4 q = pq[e];
             const SampleResult r = eval_sample<kFeatF16>(sc, make_float3(q.x, q.y, q.z), q.w);
-            rs[2 * e] = make_float4(r.trans, r.sg[0], r.sg[1], r.sg[2]);
-            rs[2 * e + 1] = make_float4(r.sg[3], r.sg[4], r.sg[5], r.sg[6]);
+            rs[2 * lane] = make_float4(r.trans, r.sg[0], r.sg[1], r.sg[2]);
+            rs[2 * lane + 1] = make_float4(r.sg[3], r.sg[4], r.sg[5], r.sg[6]);
         }
         __syncthreads();
         // ---- composite this lane's shaded samples in ray order
@@ -866,7 +867,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
                             u32x4{f.op[0], f.op[1], f.op[2], (f.bi << 13) | f.ol};
                     }
                 }
-                const float4 ra = rs[2 * e], rbv = rs[2 * e + 1];
+                const float4 ra = rs[2 * item], rbv = rs[2 * item + 1];
                 const SampleResult r = {ra.x, {ra.y, ra.z, ra.w, rbv.x, rbv.y, rbv.z, rbv.w}};
                 composite<kStats>(acc, r, cnt);
                 ++done;
