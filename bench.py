@@ -397,6 +397,20 @@ def main():
                     "visited": visited / n_rays, "occ_lookups": occ_lookups / n_rays},
         "alg_bytes_per_launch": alg_bytes,
     }
+    # the same frames with two in flight (alternating streams, as a renderer
+    # double-buffers): the tail of one frame overlaps the start of the next
+    s2 = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs2 = [out, torch.empty_like(out)]
+    for i in range(4):
+        r.render(cams, out=outs2[i % 2], stream=s2[i % 2])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        r.render(cams, out=outs2[i % 2], stream=s2[i % 2])
+    torch.cuda.synchronize()
+    ms2 = (time.perf_counter() - t0) * 1e3 / args.steps
+    res["two_in_flight"] = {"ms_per_frame": ms2, "Mrays/s": rays / (ms2 * 1e-3) / 1e6}
+    del outs2
     # the paper's level-by-level skipping (skip_mode 1) on the same frame:
     # same image, more march steps
     lv_img = torch.empty_like(out)

@@ -10,13 +10,17 @@
 //   3. each segment is marched on a uniform lattice of contracted step s
 //      (sample at each interval midpoint, last interval shortened); a sample
 //      is evaluated only if every occupancy level marks its cell occupied
-//      (Sec. 6); when a level reports an empty cell the march jumps to the
-//      first lattice sample past that cell's exit (ray-box slab test in
-//      contracted space, exact because the segment is straight);
-//   4. evaluated samples gather the 3D grid (trilinear, one brick per sample
-//      thanks to the apron) and the three planes (bilinear), dequantise each
-//      code (Eq. 8), sum (Eq. 5), decode (Eq. 6) -- density first, appearance
-//      only when alpha != 0 -- and composite (Eq. 1-2);
+//      (Sec. 6); in empty space the march jumps to the first lattice sample
+//      past the exit of an empty box (ray-box slab test in contracted space,
+//      exact because the segment is straight): by default the largest empty
+//      cube ahead, from a grid derived from the levels at upload, otherwise
+//      the empty cell of the first empty level;
+//   4. evaluated samples are parked in LDS; the wave shades up to 64 parked
+//      samples at once, whoever's they are: gather the 3D grid (trilinear,
+//      one brick per sample thanks to the apron) and the three planes
+//      (bilinear), dequantise each code (Eq. 8), sum (Eq. 5), decode
+//      (Eq. 6) -- density first, appearance only when alpha != 0; each lane
+//      then composites its own samples in ray order (Eq. 1-2);
 //   5. marching stops when the transmittance drops below t_min (Sec. 6);
 //   6. the deferred MLP h(C_d, F, d) runs once per pixel (Eq. 3, App. B).
 #include <hip/hip_runtime.h>
