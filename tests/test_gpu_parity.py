@@ -138,6 +138,20 @@ def test_skip_modes_render_the_same_image(torch, merf, tiny_scene, tiny_cams, kw
     assert ca[2] <= cb[2]
 
 
+def test_fine_occupancy_uses_chebyshev_grid(torch, merf, tiny_scene, tiny_cams):
+    say("tiny scene with a 512^3 finest occupancy level (one shared Chebyshev grid instead of octant grids)")
+    import dataclasses
+    r0, fine = tiny_scene.occ[-1]
+    up = np.repeat(np.repeat(np.repeat(fine, 512 // r0, 0), 512 // r0, 1), 512 // r0, 2)
+    sc = dataclasses.replace(tiny_scene, occ=list(tiny_scene.occ) + [(512, np.ascontiguousarray(up))])
+    a = gpu_render(torch, merf, sc, tiny_cams)
+    b = gpu_render(torch, merf, sc, tiny_cams, skip="levels")
+    base = gpu_render(torch, merf, tiny_scene, tiny_cams)
+    # the added level refines the finest one without changing any decision
+    assert np.array_equal(a, b)
+    assert np.array_equal(a, base)
+
+
 def test_ragged_batch_and_offsets(torch, merf, tiny_scene):
     say("ragged multi-camera batch")
     base = synth.tiny_camera()
