@@ -299,6 +299,22 @@ def variants_workload(steps: int):
             "variants": res}
 
 
+def two_in_flight(r, cams, out, steps):
+    """Frames rendered on two alternating streams, so consecutive frames overlap."""
+    import torch
+    s2 = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs2 = [out, torch.empty_like(out)]
+    for i in range(4):
+        r.render(cams, out=outs2[i % 2], stream=s2[i % 2])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        r.render(cams, out=outs2[i % 2], stream=s2[i % 2])
+    torch.cuda.synchronize()
+    ms2 = (time.perf_counter() - t0) * 1e3 / steps
+    return {"ms_per_frame": ms2, "Mrays/s": cams.num_pixels() / (ms2 * 1e-3) / 1e6}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -312,6 +328,8 @@ def main():
     ap.add_argument("--stress-scenes", type=int, default=32)
     ap.add_argument("--serve-requests", type=int, default=240,
                     help="requests in the serving-mix leg (0 skips it)")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="skip the two-frames-in-flight leg (its concurrent launches would blur per-kernel profiles)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after timing, run a plain device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
@@ -399,18 +417,8 @@ def main():
     }
     # the same frames with two in flight (alternating streams, as a renderer
     # double-buffers): the tail of one frame overlaps the start of the next
-    s2 = [torch.cuda.Stream(), torch.cuda.Stream()]
-    outs2 = [out, torch.empty_like(out)]
-    for i in range(4):
-        r.render(cams, out=outs2[i % 2], stream=s2[i % 2])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        r.render(cams, out=outs2[i % 2], stream=s2[i % 2])
-    torch.cuda.synchronize()
-    ms2 = (time.perf_counter() - t0) * 1e3 / args.steps
-    res["two_in_flight"] = {"ms_per_frame": ms2, "Mrays/s": rays / (ms2 * 1e-3) / 1e6}
-    del outs2
+    if not args.no_overlap:
+        res["two_in_flight"] = two_in_flight(r, cams, out, args.steps)
     # the paper's level-by-level skipping (skip_mode 1) on the same frame:
     # same image, more march steps
     lv_img = torch.empty_like(out)
