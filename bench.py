@@ -57,7 +57,19 @@ def measured_traffic():
     return t.get("bytes_per_launch")
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(scene, cams, seconds: float):
+    """The FP64 oracle on the host: a bounded sample of rows of the frame on all
+    host threads, plus a small sample on one thread."""
     import oracle
     os_ = oracle.OracleScene(scene)
     W, H = int(cams.size[0, 0]), int(cams.size[0, 1])
@@ -72,11 +84,18 @@ def cpu_baseline(scene, cams, seconds: float):
     out, _ = oracle.render(os_, cams, rows_stride=stride, row_offset=stride // 2, fragile=False, stats=False)
     dt = time.perf_counter() - t0
     n = out.shape[0]
+    # one thread, 8 rows spread over the frame
+    t1 = time.perf_counter()
+    one, _ = oracle.render(os_, cams, rows_stride=135, row_offset=67, fragile=False, stats=False, nthreads=1)
+    dt1 = time.perf_counter() - t1
     import numpy as np
     rows = np.arange(stride // 2, H, stride)
     sel = (rows[:, None] * W + np.arange(W)[None, :]).reshape(-1)
     return ({"value": n / dt / 1e6, "unit": "Mrays/s", "cores": oracle.max_threads(), "kind": "oracle",
-             "sample": f"every {stride}th row of the {W}x{H} frame ({n} rays, {dt:.1f} s, FP64 C, OpenMP)"},
+             "sample": f"every {stride}th row of the {W}x{H} frame ({n} rays, {dt:.1f} s, FP64 C, OpenMP)",
+             "one_thread_Mrays/s": one.shape[0] / dt1 / 1e6,
+             "one_thread_sample": f"every 135th row ({one.shape[0]} rays, {dt1:.1f} s)",
+             "cpu_model": cpu_model()},
             (out, sel))
 
 
