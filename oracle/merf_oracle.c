@@ -544,8 +544,10 @@ long or_render(const or_scene *s, const or_camera *cams, int ncams, const or_par
         for (int i = row_offset; i < cam->height; i += rows_stride) ++nrows;
         long base = total;
 #ifdef _OPENMP
-        if (nthreads > 0) omp_set_num_threads(nthreads);
-#pragma omp parallel for schedule(dynamic, 1)
+        /* a thread count for this call only (omp_set_num_threads would
+         * persist into later calls) */
+        const int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
 #endif
         for (int ri = 0; ri < nrows; ++ri) {
             int i = row_offset + ri * rows_stride;
