@@ -6,13 +6,16 @@ Workload: the full-size plain FP32 scene (512^3 sparse grid of 8^3 blocks at
 pyramid, content to ||x||_inf = 100 before contraction) rendered from one
 1920x1080 camera inside the unit cube.  A step is one merf_render call of that
 frame (ray generation, contraction, skipping, gathers, compositing and the
-deferred MLP -- the whole hot path, one kernel launch).  Inputs are resident
-in device memory before timing starts.
+deferred MLP -- the whole hot path in one render kernel, after a small
+prepass that orders the tiles heaviest first).  Steps run back to back on
+one stream; inputs are resident in device memory before timing starts.
 
 Prints ONE JSON line.  Besides throughput it reports:
-  roofline      algorithmic gather bytes per launch / average kernel time
-                (HIP events on the launch stream), against HBM peak;
-  latency_ms    p50 / p99 of per-frame GPU time;
+  roofline      algorithmic gather bytes per launch / average render-kernel
+                time (HIP events recorded around that kernel on its stream),
+                against HBM peak;
+  latency_ms    p50 / p99 of frames rendered alone (host wall time from the
+                call until the frame is done, prepass included);
   cpu_baseline  the FP64 oracle on a bounded row sample of the same frame.
 """
 import argparse
@@ -318,6 +321,77 @@ def variants_workload(steps: int):
             "variants": res}
 
 
+class KernelTimer:
+    """Pairs of HIP timing events created without the system-scope cache
+    flush that an ordinary event record performs (hipEventDisableSystemFence):
+    the flush would slow the kernel being timed and the one after it."""
+
+    DISABLE_SYSTEM_FENCE = 0x20000000
+
+    def __init__(self, n):
+        import ctypes as C
+        import torch
+        torch.cuda.init()
+        self.C = C
+        self.hip = C.CDLL("libamdhip64.so.7")       # the runtime torch already loaded
+        self.hip.hipEventCreateWithFlags.argtypes = [C.POINTER(C.c_void_p), C.c_uint]
+        self.hip.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [C.c_void_p]
+        self.ev = []
+        for _ in range(2 * n):
+            e = C.c_void_p()
+            assert self.hip.hipEventCreateWithFlags(C.byref(e), self.DISABLE_SYSTEM_FENCE) == 0
+            self.ev.append(e)
+
+    def pair(self, i):
+        return self.ev[2 * i], self.ev[2 * i + 1]
+
+    def ms(self, a, b):
+        t = self.C.c_float()
+        assert self.hip.hipEventElapsedTime(self.C.byref(t), a, b) == 0
+        return t.value
+
+    def close(self):
+        for e in self.ev:
+            self.hip.hipEventDestroy(e)
+
+
+def timed_frames(merf, r, cams, img, n, **kw):
+    """Mean render-kernel and whole-frame GPU times (ms) of n frames rendered
+    back to back into img with render parameters kw."""
+    import numpy as np
+    import torch
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        r.render(cams, out=img, **kw)
+    tm = KernelTimer(n)
+    torch.cuda.synchronize()
+    for i in range(n):
+        merf.render_timed(r.handle, cams, img, *tm.pair(i), **kw)
+    torch.cuda.synchronize()
+    kern = [tm.ms(*tm.pair(i)) for i in range(n)]
+    frame = [tm.ms(tm.pair(i - 1)[1], tm.pair(i)[1]) for i in range(1, n)]
+    tm.close()
+    return float(np.mean(kern)), float(np.mean(frame))
+
+
+def isolated_latency(r, cams, img, n, **kw):
+    """Host wall time (ms) of n frames each rendered alone: render, then wait
+    for it, so nothing overlaps (the tile-order prepass included)."""
+    import numpy as np
+    import torch
+    for _ in range(3):
+        r.render(cams, out=img, **kw)
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(n):
+        t0 = time.perf_counter()
+        r.render(cams, out=img, **kw)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t0) * 1e3)
+    return {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)), "mean": float(np.mean(lat))}
+
+
 def two_in_flight(r, cams, out, steps):
     """Frames rendered on two alternating streams, so consecutive frames overlap."""
     import torch
@@ -393,16 +467,20 @@ def main():
         r.render(cams, out=out)
     torch.cuda.synchronize()
 
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    # per step, the library records a pair of events right around the render
+    # kernel on its stream (the frame's tile-order prepass runs before, on
+    # the library's own stream, overlapping the previous frame)
+    tm = KernelTimer(args.steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        ev[i][0].record(stream)
-        r.render(cams, out=out)
-        ev[i][1].record(stream)
+        merf.render_timed(r.handle, cams, out, *tm.pair(i))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    per = np.array([a.elapsed_time(b) for a, b in ev])          # ms, GPU time per frame
+    per = np.array([tm.ms(*tm.pair(i)) for i in range(args.steps)])        # ms, render kernel
+    # ms from one frame's end to the next one's: the GPU time per frame
+    frame = np.array([tm.ms(tm.pair(i - 1)[1], tm.pair(i)[1]) for i in range(1, args.steps)])
+    tm.close()
 
     ms_per_step = wall * 1e3 / args.steps
     kernel_ms = float(per.mean())
@@ -429,7 +507,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic},
         "kernel_ms": kernel_ms,
-        "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99))},
+        "frame_gpu_ms": float(frame.mean()),
+        "latency_ms": isolated_latency(r, cams, out, 100),
         "per_ray": {"evaluated": evaluated / n_rays, "contributing": contributing / n_rays,
                     "visited": visited / n_rays, "occ_lookups": occ_lookups / n_rays},
         "alg_bytes_per_launch": alg_bytes,
@@ -438,23 +517,22 @@ def main():
     # double-buffers): the tail of one frame overlaps the start of the next
     if not args.no_overlap:
         res["two_in_flight"] = two_in_flight(r, cams, out, args.steps)
+    # the same frame with the tiles in plain order (no cost prepass)
+    pl_img = torch.empty_like(out)
+    pl_kernel, pl_frame = timed_frames(merf, r, cams, pl_img, 20, order="plain")
+    res["plain_order"] = {"kernel_ms": pl_kernel, "frame_gpu_ms": pl_frame,
+                          "Mrays/s": rays / (pl_frame * 1e-3) / 1e6,
+                          "latency_ms": isolated_latency(r, cams, pl_img, 100, order="plain"),
+                          "same_image": bool(torch.equal(pl_img, out))}
+    del pl_img
     # the paper's level-by-level skipping (skip_mode 1) on the same frame:
     # same image, more march steps
     lv_img = torch.empty_like(out)
     st_lv = torch.zeros(8, dtype=torch.int64, device="cuda")
     r.render(cams, out=lv_img, stats=st_lv, skip="levels")
-    for _ in range(3):
-        r.render(cams, out=lv_img, skip="levels")
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(20):
-        r.render(cams, out=lv_img, skip="levels")
-    e1.record(stream)
-    torch.cuda.synchronize()
-    lv_ms = e0.elapsed_time(e1) / 20
+    lv_kernel, lv_ms = timed_frames(merf, r, cams, lv_img, 20, skip="levels")
     c_lv = st_lv.cpu().numpy()
-    res["skip_levels"] = {"kernel_ms": lv_ms, "Mrays/s": rays / (lv_ms * 1e-3) / 1e6,
+    res["skip_levels"] = {"kernel_ms": lv_kernel, "frame_gpu_ms": lv_ms, "Mrays/s": rays / (lv_ms * 1e-3) / 1e6,
                           "visited_per_ray": float(c_lv[2]) / n_rays, "occ_lookups_per_ray": float(c_lv[1]) / n_rays,
                           "same_image": bool(torch.equal(lv_img, out))}
     del lv_img
@@ -465,6 +543,7 @@ def main():
     for _ in range(3):
         rec.replay()
     torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(20):
         rec.replay()
@@ -476,6 +555,7 @@ def main():
                             "replay_GB/s": gather_bytes / (rp_ms * 1e-3) / 1e9,
                             "render_GB/s": gather_bytes / (kernel_ms * 1e-3) / 1e9,
                             "render_frac_of_replay": rp_ms / kernel_ms,
+                            "frame_frac_of_replay": rp_ms / float(frame.mean()),
                             "max_samples_per_ray": int(counts.max()),
                             "unrecorded_samples": int(np.maximum(counts - rec.cap, 0).sum()),
                             "same_image": bool(torch.equal(rec.image, out))}
@@ -486,18 +566,9 @@ def main():
     for name, mlp, feat in (("mlp_f16", "f16", "f32"), ("mlp_bf16", "bf16", "f32"),
                             ("feat_f16_mlp_f16", "f16", "f16"), ("feat_f16_mlp_bf16", "bf16", "f16")):
         img = torch.empty_like(out)
-        for _ in range(3):
-            r.render(cams, out=img, mlp_prec=mlp, feat_prec=feat)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(20):
-            r.render(cams, out=img, mlp_prec=mlp, feat_prec=feat)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / 20
-        prec[name] = {"mlp": mlp, "features": feat, "kernel_ms": ms, "Mrays/s": rays / (ms * 1e-3) / 1e6,
-                      "_img": img}
+        k_ms, ms = timed_frames(merf, r, cams, img, 20, mlp_prec=mlp, feat_prec=feat)
+        prec[name] = {"mlp": mlp, "features": feat, "kernel_ms": k_ms, "frame_gpu_ms": ms,
+                      "Mrays/s": rays / (ms * 1e-3) / 1e6, "_img": img}
     res["precision"] = prec
     if args.copy_probe_mb > 0:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters read

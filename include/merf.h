@@ -117,6 +117,15 @@ typedef struct {
                                              of a sample is left in one step);
                                              1 = the levels themselves, coarse to fine,
                                              leaving one empty cell per step (Sec. 6) */
+    int32_t tile_order;                   /* order in which the 8x8 tiles of a launch run,
+                                             same image either way: 0 = estimated
+                                             heaviest first for launches of 8192 to
+                                             131072 tiles (a prepass marches 4 rays of
+                                             each tile to their first occupied sample;
+                                             the first calls on a device allocate up to
+                                             8 work buffers of 640 KB, kept until the
+                                             process ends), plain order otherwise;
+                                             1 = plain order */
     uint64_t *stats_dev;                  /* NULL, or device uint64[8] to which the render
                                              ADDS: [0] rays, [1] occupancy lookups
                                              (skip_mode 0: distance-grid lookups),

@@ -7,9 +7,9 @@
  * bound what those gathers alone can reach, merf_record_gathers renders a
  * view while recording, for every evaluated sample, the texel offsets it
  * reads; merf_replay_gathers then re-issues exactly those loads, in the same
- * order, tile layout and wave shape, with no other arithmetic.  The ratio of
- * replay time to render time is the fraction of the gather bound the renderer
- * reaches.
+ * order, tile order, tile layout and wave shape, with no other arithmetic.
+ * The ratio of replay time to render time is the fraction of the gather
+ * bound the renderer reaches.
  *
  * Same error conventions as merf.h (0 = MERF_OK, negative codes,
  * merf_last_error()).
@@ -37,17 +37,34 @@ int merf_gather_slots(const merf_camera *cams, int32_t n_cams, int32_t *n_slots)
  * receives, for evaluated sample k < cap of slot q, at [k][q]: the byte
  * offsets of the (u, v) texels of the three planes and (brick index entry
  * << 13 | byte offset in the brick) of the grid footprint.  Samples k >= cap
- * are counted but not recorded.  Requires (grid_res / 8)^3 <= 2^19 so that
- * the grid word packs.  Asynchronous on hip_stream.
+ * are counted but not recorded.  order_dev: device int32[n_slots / 64]
+ * receives the tile order of the launch (entry i: the tile workgroup slot i
+ * rendered; p->tile_order decides it as in merf_render).  Requires
+ * (grid_res / 8)^3 <= 2^19 so that the grid word packs.  Asynchronous on
+ * hip_stream.
  * Errors: MERF_E_INVALID for a bad handle, camera, parameter, cap < 1, NULL
  * buffers or a grid too large to pack; MERF_E_DEVICE if the launch fails.
  */
 int merf_record_gathers(merf_scene_t s, const merf_camera *cams, int32_t n_cams, const merf_render_params *p,
-                        uint32_t *rec_dev, int32_t cap, int32_t *count_dev, float *out_rgba_dev, void *hip_stream);
+                        uint32_t *rec_dev, int32_t cap, int32_t *count_dev, int32_t *order_dev, float *out_rgba_dev,
+                        void *hip_stream);
 
 /*
- * Re-issue the recorded loads of n_slots slots (rec_dev, count_dev and cap as
- * given to merf_record_gathers for scene s) and write one float4 per slot to
+ * Render cams (at most 16, one launch) exactly as merf_render does, and
+ * record ev_start and ev_end (hipEvent_t, created by the caller with timing
+ * enabled) on hip_stream right before and right after the render kernel, so
+ * that their elapsed time is that kernel's duration alone (the tile-order
+ * prepass of the launch runs before ev_start).  Asynchronous on hip_stream.
+ * Errors: MERF_E_INVALID for a bad handle, camera, parameter or NULL
+ * argument; MERF_E_DEVICE if a launch or event record fails.
+ */
+int merf_render_timed(merf_scene_t s, const merf_camera *cams, int32_t n_cams, const merf_render_params *p,
+                      float *out_rgba_dev, void *ev_start, void *ev_end, void *hip_stream);
+
+/*
+ * Re-issue the recorded loads of n_slots slots (rec_dev, count_dev, cap and
+ * order_dev as given to merf_record_gathers for scene s), with the tiles in
+ * the recorded order, and write one float4 per slot to
  * out_dev (device, n_slots * 4 floats): its recorded sample count, then
  * values with no meaning that keep the loads live.  Asynchronous on
  * hip_stream.
@@ -55,7 +72,7 @@ int merf_record_gathers(merf_scene_t s, const merf_camera *cams, int32_t n_cams,
  * 64, cap < 1 or NULL buffers; MERF_E_DEVICE if the launch fails.
  */
 int merf_replay_gathers(merf_scene_t s, const uint32_t *rec_dev, const int32_t *count_dev, int32_t cap,
-                        int32_t n_slots, float *out_dev, void *hip_stream);
+                        const int32_t *order_dev, int32_t n_slots, float *out_dev, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -204,6 +204,122 @@ size_t scene_device_bytes(const merf_scene_desc *desc) {
     return make_layout(desc, count_bricks(desc)).total;
 }
 
+namespace {
+
+// Work buffers of the tile order (cost keys and order of up to
+// kOrderMaxTiles tiles).  The prepass runs on a stream of the library's own
+// (one per device), since it reads only the resident scene and these
+// buffers: it need not wait for the caller's earlier work, so it overlaps
+// the previous frame's render.  The caller's stream waits for its event
+// `ready`.  A buffer is free again once the event `done`, recorded after the
+// render that read it, has completed; a device has at most kOrderBufs, after
+// which the prepass waits (on the device) for the buffer used longest ago.
+// Buffers and streams are held until the process ends.
+struct OrderBuf {
+    int device;
+    uint8_t *keys;
+    uint32_t *group_counts;
+    int32_t *order;
+    hipEvent_t ready, done;
+    uint64_t last_use;                           // 0: not used yet
+};
+constexpr int kOrderBufs = 8;
+// The events order device work only (the host merely asks whether a buffer
+// is free), so they skip the system-scope cache flush of an event record.
+constexpr unsigned kOrderEventFlags = hipEventDisableTiming | hipEventDisableSystemFence;
+std::mutex g_order_mutex;
+std::vector<OrderBuf> g_order_bufs;
+std::vector<std::pair<int, hipStream_t>> g_order_streams;
+uint64_t g_order_uses = 0;
+
+// The library's prepass stream of a device, or null (caller holds g_order_mutex).
+hipStream_t order_stream(int device) {
+    for (auto &ds : g_order_streams)
+        if (ds.first == device) return ds.second;
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    g_order_streams.emplace_back(device, st);
+    return st;
+}
+
+// Index of a buffer the prepass on stream may use, or -1 (caller holds
+// g_order_mutex).
+int order_buffer(int device, hipStream_t stream) {
+    int oldest = -1, n = 0;
+    for (int i = 0; i < (int)g_order_bufs.size(); ++i) {
+        const OrderBuf &b = g_order_bufs[i];
+        if (b.device != device) continue;
+        ++n;
+        if (b.last_use == 0 || hipEventQuery(b.done) == hipSuccess) return i;
+        if (oldest < 0 || b.last_use < g_order_bufs[oldest].last_use) oldest = i;
+    }
+    if (n < kOrderBufs) {
+        OrderBuf b{device, nullptr, nullptr, nullptr, nullptr, nullptr, 0};
+        if (hipMalloc(&b.keys, kOrderMaxTiles) == hipSuccess &&
+            hipMalloc(&b.group_counts, sizeof(uint32_t) * (kOrderMaxTiles / 16)) == hipSuccess &&
+            hipMalloc(&b.order, sizeof(int32_t) * kOrderMaxTiles) == hipSuccess &&
+            hipEventCreateWithFlags(&b.ready, kOrderEventFlags) == hipSuccess &&
+            hipEventCreateWithFlags(&b.done, kOrderEventFlags) == hipSuccess) {
+            g_order_bufs.push_back(b);
+            return (int)g_order_bufs.size() - 1;
+        }
+        if (b.keys) (void)hipFree(b.keys);
+        if (b.group_counts) (void)hipFree(b.group_counts);
+        if (b.order) (void)hipFree(b.order);
+        if (b.ready) (void)hipEventDestroy(b.ready);
+    }
+    if (oldest >= 0 && hipStreamWaitEvent(stream, g_order_bufs[oldest].done, 0) == hipSuccess) return oldest;
+    return -1;
+}
+
+bool capturing(hipStream_t stream) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+}
+
+}  // namespace
+
+int render_launch(const DevScene &ds, RenderBatch &rb, int tile_order, hipStream_t stream, int32_t *order_out,
+                  hipEvent_t ev_start, hipEvent_t ev_end) {
+    std::unique_lock<std::mutex> lock(g_order_mutex, std::defer_lock);
+    int buf = -1;
+    if (tile_order == 0 && rb.total_tiles >= kOrderMinTiles && rb.total_tiles <= kOrderMaxTiles &&
+        !capturing(stream)) {
+        lock.lock();
+        int device = 0;
+        hipStream_t ps = hipGetDevice(&device) == hipSuccess ? order_stream(device) : nullptr;
+        if (ps) buf = order_buffer(device, ps);
+        (void)hipGetLastError();              // a not-ready event query is no error
+        if (buf >= 0) {
+            const OrderBuf &b = g_order_bufs[buf];
+            hipError_t e = launch_tile_order(ds, rb, b.keys, b.group_counts, b.order, ps);
+            if (e == hipSuccess) e = hipEventRecord(b.ready, ps);
+            if (e == hipSuccess) e = hipStreamWaitEvent(stream, b.ready, 0);
+            if (e != hipSuccess) return hip_fail(e, "tile order");
+            rb.order = b.order;
+        }
+    }
+    hipError_t e = ev_start ? hipEventRecord(ev_start, stream) : hipSuccess;
+    if (e != hipSuccess) return hip_fail(e, "start event");
+    e = launch_render(ds, rb, stream);
+    if (e != hipSuccess) return hip_fail(e, "render launch");
+    e = ev_end ? hipEventRecord(ev_end, stream) : hipSuccess;
+    if (e != hipSuccess) return hip_fail(e, "end event");
+    if (order_out) {
+        e = rb.order ? hipMemcpyAsync(order_out, rb.order, sizeof(int32_t) * (size_t)rb.total_tiles,
+                                      hipMemcpyDeviceToDevice, stream)
+                     : launch_identity_order(order_out, rb.total_tiles, stream);
+        if (e != hipSuccess) return hip_fail(e, "tile order copy");
+    }
+    if (buf >= 0) {
+        OrderBuf &b = g_order_bufs[buf];
+        e = hipEventRecord(b.done, stream);
+        if (e != hipSuccess) return hip_fail(e, "tile order event");
+        b.last_use = ++g_order_uses;
+    }
+    return MERF_OK;
+}
+
 int check_params(const merf_render_params *p, int res, float *step_out) {
     if (!p) return fail(MERF_E_INVALID, "render params are NULL");
     if (p->struct_size != sizeof(merf_render_params))
@@ -215,6 +331,8 @@ int check_params(const merf_render_params *p, int res, float *step_out) {
     if (p->mlp_prec < 0 || p->mlp_prec > 2) return fail(MERF_E_INVALID, "mlp_prec %d not in {0, 1, 2}", p->mlp_prec);
     if (p->feat_prec != 0 && p->feat_prec != 1) return fail(MERF_E_INVALID, "feat_prec %d not in {0, 1}", p->feat_prec);
     if (p->skip_mode != 0 && p->skip_mode != 1) return fail(MERF_E_INVALID, "skip_mode %d not in {0, 1}", p->skip_mode);
+    if (p->tile_order != 0 && p->tile_order != 1)
+        return fail(MERF_E_INVALID, "tile_order %d not in {0, 1}", p->tile_order);
     *step_out = step;
     return MERF_OK;
 }
@@ -460,8 +578,7 @@ int merf_render(merf_scene_t s, const merf_camera *cams, int32_t n_cams, const m
             ++first;
         }
         if (rb.n_cams == 0) return fail(MERF_E_INVALID, "camera %d alone exceeds one launch", first);
-        hipError_t e = launch_render(s->ds, rb, stream);
-        if (e != hipSuccess) return hip_fail(e, "render launch");
+        if ((rc = render_launch(s->ds, rb, p->tile_order, stream))) return rc;
     }
     return MERF_OK;
 }

@@ -21,6 +21,14 @@ constexpr int kTile = 8;                         // a wave renders an 8x8 pixel 
 constexpr int kCamsPerLaunch = 16;               // cameras carried in one launch's arguments
 constexpr int kMaxDistRes = 1024;                // finest occupancy resolution (distance grid)
 constexpr int kOctMaxRes = 256;                  // up to this r_f the grid has eight octant forms
+// Tile order of a launch: a prepass estimates each tile's cost from
+// kCostRays of its rays, and the tiles run heaviest first.  Launches of fewer
+// than kOrderMinTiles tiles (all of them start at once on 256 CUs) or more
+// than kOrderMaxTiles (one workgroup sorts the keys) keep the plain order.
+constexpr int kCostRays = 4;
+constexpr int kCostKeys = kCostRays + 1;         // key = rays of the tile that reach occupied space
+constexpr int kOrderMinTiles = 8192;
+constexpr int kOrderMaxTiles = 1 << 17;
 
 // Scene as laid out in device memory.
 //   brick_index  int32 [(L/8)^3] z-major: brick slot; blocks whose brick would
@@ -90,19 +98,31 @@ struct RenderBatch {
     uint32_t *rec;
     int32_t *rec_count;
     int32_t rec_cap;
+    // tile order (null = plain): workgroup slot i renders tile order[i]
+    const int32_t *order;
     DevCamera cams[kCamsPerLaunch];
 };
 
 // Launchers (merf_render.hip).
 hipError_t launch_render(const DevScene &sc, const RenderBatch &rb, hipStream_t stream);
+// Heaviest-first tile order of a launch: keys (uint8 [kOrderMaxTiles])
+// receive the cost keys, group_counts (uint32 [kOrderMaxTiles / 16]) their
+// counts per group of tiles, order (int32 [total_tiles]) the tiles sorted by
+// key, highest first, ascending tile within a key.  Needs total_tiles <=
+// kOrderMaxTiles.
+hipError_t launch_tile_order(const DevScene &sc, const RenderBatch &rb, uint8_t *keys, uint32_t *group_counts,
+                             int32_t *order, hipStream_t stream);
+// order[i] = i for i < n (the plain order, for the gather replay).
+hipError_t launch_identity_order(int32_t *order, int n, hipStream_t stream);
 // The kernel a batch runs and its launch shape (for graph nodes).
 const void *render_kernel(const RenderBatch &rb);
 dim3 render_grid(const RenderBatch &rb);
 constexpr int kRenderBlock = 64;
 // Gather replay (measurement): re-issues the recorded texel loads of a
-// launch of total_tiles tiles with no arithmetic; out: float4 per slot.
+// launch of total_tiles tiles with no arithmetic, in the launch's tile order
+// (null: plain); out: float4 per slot.
 hipError_t launch_gather_replay(const DevScene &sc, const uint32_t *rec, const int32_t *rec_count, int cap,
-                                int total_tiles, float *out, hipStream_t stream);
+                                const int32_t *order, int total_tiles, float *out, hipStream_t stream);
 hipError_t launch_dequant(const uint8_t *codes, int64_t n, float m, int prec, void *out, hipStream_t stream);
 // merf_ingest.hip: brick_pos[i] = bx | by << 10 | bz << 20 of brick slot i.
 hipError_t launch_pack_bricks(const uint8_t *blocks, const int32_t *block_index, const int32_t *brick_pos,

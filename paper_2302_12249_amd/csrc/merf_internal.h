@@ -33,4 +33,14 @@ int check_camera(const merf_camera &c, int index);
 void begin_batch(RenderBatch &rb, const merf_render_params &p, float step);
 bool add_camera(RenderBatch &rb, const merf_camera &c, float *out);
 
+// Launch one render batch on stream: heaviest tiles first when tile_order is
+// 0 and the launch has kOrderMinTiles..kOrderMaxTiles tiles (and the stream
+// is not capturing a graph), plain order otherwise.  order_out (device
+// int32[total_tiles], or null) receives the order used: order_out[i] is the
+// tile of workgroup slot i.  ev_start / ev_end (or null) are recorded on
+// stream right before and after the render kernel.  Returns MERF_OK or a
+// recorded error.
+int render_launch(const DevScene &ds, RenderBatch &rb, int tile_order, hipStream_t stream,
+                  int32_t *order_out = nullptr, hipEvent_t ev_start = nullptr, hipEvent_t ev_end = nullptr);
+
 }  // namespace merf

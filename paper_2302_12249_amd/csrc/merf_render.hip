@@ -463,6 +463,62 @@ __device__ __forceinline__ void open_segment(float3 o, float3 d, float ta, int r
     s.doff = oct_stride * (uint32_t)((s.iex < 0.0f ? 1 : 0) | (s.iey < 0.0f ? 2 : 0) | (s.iez < 0.0f ? 4 : 0));
 }
 
+// Empty-space grid of the segment's octant at contracted point p.  Returns
+// the byte D of p's cell: D > 0 means the cube of D cells a side with a
+// corner at that cell, extending the way the segment travels, is empty; 0
+// means the cell is occupied (the cube is the cell itself).  ue is the
+// segment parameter at which the cube ends (slab test).
+__device__ __forceinline__ int dist_lookup(const DevScene &sc, const Segment &s, float3 p, float &ue) {
+    const int r = sc.dist_res;
+    // cell of p: (p + 2) r / 4 rounded down; contracted points have p >= -2
+    // up to rounding, so truncation equals the floor and no lower clamp is
+    // needed
+    const float os = sc.dist_scale, os2 = sc.dist_off;
+    const int qx = min((int)fmaf(p.x, os, os2), r - 1);
+    const int qy = min((int)fmaf(p.y, os, os2), r - 1);
+    const int qz = min((int)fmaf(p.z, os, os2), r - 1);
+    const int D = load_at<uint8_t>(sc.dist, s.doff + cell_offset(qx, qy, qz, r));
+    const int ext = D > 0 ? D - 1 : 0;
+    const float h = sc.dist_cell;
+    const float bx = (float)(s.iex > 0.0f ? qx + ext + 1 : qx - ext) * h - 2.0f;
+    const float by = (float)(s.iey > 0.0f ? qy + ext + 1 : qy - ext) * h - 2.0f;
+    const float bz = (float)(s.iez > 0.0f ? qz + ext + 1 : qz - ext) * h - 2.0f;
+    const float tx = (bx - s.A.x) * s.iex;
+    const float ty = (by - s.A.y) * s.iey;
+    const float tz = (bz - s.A.z) * s.iez;
+    ue = fminf(tx, fminf(ty, tz));
+    return D;
+}
+
+// Next lattice interval after leaving empty space at segment parameter
+// uexit: the first whose midpoint lies past the exit, and at least k + 1.
+__device__ __forceinline__ int skip_past(const Segment &s, float uexit, float istep) {
+    const float kn = floorf((uexit - kSkipGuard) * istep - 0.5f) + 1.0f;
+    const int knext = kn > (float)s.n ? s.n : (int)fmaxf(kn, 0.0f);
+    return max(s.k + 1, knext);
+}
+
+// Pinhole ray through the centre of pixel (px, py) (unit direction).
+__device__ __forceinline__ void pixel_ray(const DevCamera &cam, int px, int py, float3 &o, float3 &d) {
+    const float vx = ((float)px + 0.5f - cam.cx) * cam.inv_fx;
+    const float vy = ((float)py + 0.5f - cam.cy) * cam.inv_fy;
+    d = make_float3(fmaf(cam.c2w[0], vx, fmaf(cam.c2w[1], vy, cam.c2w[2])),
+                    fmaf(cam.c2w[4], vx, fmaf(cam.c2w[5], vy, cam.c2w[6])),
+                    fmaf(cam.c2w[8], vx, fmaf(cam.c2w[9], vy, cam.c2w[10])));
+    const float inv = __builtin_amdgcn_rsqf(d.x * d.x + d.y * d.y + d.z * d.z);
+    d.x *= inv; d.y *= inv; d.z *= inv;
+    o = make_float3(cam.c2w[3], cam.c2w[7], cam.c2w[11]);
+}
+
+// Camera of a launch tile: the last camera whose first tile is <= tile.
+__device__ __forceinline__ int camera_of(const RenderBatch &rb, int tile) {
+    int c = 0;
+#pragma unroll
+    for (int i = 1; i < kCamsPerLaunch; ++i)
+        if (i < rb.n_cams && tile >= rb.cams[i].tile_start) c = i;
+    return c;
+}
+
 // Deferred MLP (Eq. 3, App. B) for the 64 pixels of a wave on the matrix
 // cores.  Each layer is computed transposed, H^T = W^T X^T, over 4 blocks of
 // 16 pixels: the output of one layer (lane l holds hidden units 4(l/16) .. +3
@@ -652,7 +708,9 @@ constexpr int kLdsFloats = MlpLds<kPrec>::kFloats > kParkFloats ? MlpLds<kPrec>:
 template <bool kStats, int kMlpPrec, bool kFeatF16, bool kLevels>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_render(const DevScene sc, const RenderBatch rb) {
     __shared__ float lds[kLdsFloats<kMlpPrec>];
-    const int tile = xcd_remap((int)blockIdx.x, rb.total_tiles);
+    const int slot = xcd_remap((int)blockIdx.x, rb.total_tiles);
+    int tile = rb.order ? rb.order[slot] : slot;
+    if ((unsigned)tile >= (unsigned)rb.total_tiles) tile = slot;   // never leave the launch
     int c = 0;
 #pragma unroll
     for (int i = 1; i < kCamsPerLaunch; ++i)
@@ -734,31 +792,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
                 int empty = -1;
                 float uexit = 0.0f;
                 if constexpr (!kLevels) {
-                    // empty-space grid of the segment's octant: a value D > 0
-                    // means the cube of D cells a side with a corner at this
-                    // cell, extending in the segment's directions, is empty;
-                    // leave the whole cube (D = 0: occupied, the cube is the
-                    // cell itself)
+                    // empty-space grid: leave the whole empty cube ahead, or
+                    // remember the occupied cell
                     if (!(um < known[0])) {
-                        const int r = sc.dist_res;
-                        // cell of p: (p + 2) r / 4 rounded down; contracted
-                        // points have p >= -2 up to rounding, so truncation
-                        // equals the floor and no lower clamp is needed
-                        const float os = sc.dist_scale, os2 = sc.dist_off;
-                        const int qx = min((int)fmaf(p.x, os, os2), r - 1);
-                        const int qy = min((int)fmaf(p.y, os, os2), r - 1);
-                        const int qz = min((int)fmaf(p.z, os, os2), r - 1);
                         if (kStats) ++cnt.occ_lookups;
-                        const int D = load_at<uint8_t>(sc.dist, s.doff + cell_offset(qx, qy, qz, r));
-                        const int ext = D > 0 ? D - 1 : 0;
-                        const float h = sc.dist_cell;
-                        const float bx = (float)(s.iex > 0.0f ? qx + ext + 1 : qx - ext) * h - 2.0f;
-                        const float by = (float)(s.iey > 0.0f ? qy + ext + 1 : qy - ext) * h - 2.0f;
-                        const float bz = (float)(s.iez > 0.0f ? qz + ext + 1 : qz - ext) * h - 2.0f;
-                        const float tx = (bx - s.A.x) * s.iex;
-                        const float ty = (by - s.A.y) * s.iey;
-                        const float tz = (bz - s.A.z) * s.iez;
-                        const float ue = fminf(tx, fminf(ty, tz));
+                        float ue;
+                        const int D = dist_lookup(sc, s, p, ue);
                         if (D == 0) {
                             known[0] = ue - kSkipGuard;
                         } else {
@@ -826,9 +865,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
                 }
                 // leave the empty cell
                 // first lattice interval whose midpoint lies past the exit
-                float kn = floorf((uexit - kSkipGuard) * istep - 0.5f) + 1.0f;
-                int knext = kn > (float)s.n ? s.n : (int)fmaxf(kn, 0.0f);
-                s.k = max(s.k + 1, knext);
+                s.k = skip_past(s, uexit, istep);
             } while (false);
         }
         // ---- shade: parked samples numbered level by level (all first
@@ -916,6 +953,160 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     }
 }
 
+// Tile cost for the launch order.  kCostRays rays of every 8x8 tile (pixels
+// (2,2), (5,2), (2,5) and (5,5) of the tile, clamped to the image) march
+// through empty space, as the renderer does, to their first occupied sample;
+// the key of a tile is the number of its rays that reach one.  Only rays
+// that reach occupied space gather, shade and composite, so tiles with higher
+// keys take longer; a march longer than kCostSteps steps also counts as a hit.
+constexpr int kCostSteps = 64;
+constexpr int kGroupTiles = 64 / kCostRays;                   // tiles of one k_tile_cost wave
+constexpr int kCountBits = kGroupTiles < 32 ? 5 : 7;           // a group's count of one key
+constexpr int kScanBits = 64 / kCostKeys;                      // a workgroup's count of one key
+static_assert(kCostKeys * kCountBits <= 32 && 64 * kGroupTiles < (1 << kScanBits), "count fields");
+__global__ __launch_bounds__(64) void k_tile_cost(const DevScene sc, const RenderBatch rb, uint8_t *__restrict__ keys,
+                                                  uint32_t *__restrict__ group_counts) {
+    const int g = (int)blockIdx.x * 64 + (int)threadIdx.x;
+    const int tile = g / kCostRays, sub = g % kCostRays;
+    bool hit = false;
+    if (tile < rb.total_tiles) {
+        const DevCamera &cam = rb.cams[camera_of(rb, tile)];
+        const int lt = tile - cam.tile_start;
+        const int px = min((lt % cam.tiles_x) * kTile + (kCostRays == 1 ? 4 : (sub & 1) ? 5 : 2), cam.width - 1);
+        const int py = min((lt / cam.tiles_x) * kTile + (kCostRays == 1 ? 4 : (sub & 2) ? 5 : 2), cam.height - 1);
+        float3 o, d;
+        pixel_ray(cam, px, py, o, d);
+        const float step = rb.step, istep = rb.inv_step;
+        Segment s;
+        const Candidates C = make_candidates(o, d);
+        const float c1 = next_candidate(C, 0.0f);
+        open_segment(o, d, 0.0f, region_at(o, d, c1 < kInf ? 0.5f * c1 : 1.0f), istep, sc.dist_oct_stride, s);
+        int nseg = 1;
+        hit = true;
+        for (int it = 0; it < kCostSteps; ++it) {
+            if (s.k >= s.n) {
+                if (!(s.tb < kInf) || nseg >= 8) {
+                    hit = false;
+                    break;
+                }
+                open_segment(o, d, s.tb, s.reg_next, istep, sc.dist_oct_stride, s);
+                ++nseg;
+                continue;
+            }
+            const float u0 = (float)s.k * step;
+            const float u1 = fminf(u0 + step, s.len);
+            const float um = 0.5f * (u0 + u1);
+            const float3 p = make_float3(fmaf(um, s.e.x, s.A.x), fmaf(um, s.e.y, s.A.y), fmaf(um, s.e.z, s.A.z));
+            float ue;
+            if (dist_lookup(sc, s, p, ue) == 0) break;
+            s.k = skip_past(s, ue, istep);
+        }
+    }
+    // the kCostRays rays of a tile are consecutive lanes
+    const uint64_t b = __ballot(hit);
+    const int key = __popcll((b >> ((int)threadIdx.x & ~(kCostRays - 1))) & ((1ull << kCostRays) - 1));
+    const bool head = tile < rb.total_tiles && sub == 0;
+    if (head) keys[tile] = (uint8_t)key;
+    // the keys of the wave's kGroupTiles tiles (a group), counted per key in
+    // kCountBits-bit fields
+    uint32_t packed = 0u;
+#pragma unroll
+    for (int k = 0; k < kCostKeys; ++k) packed |= (uint32_t)__popcll(__ballot(head && key == k)) << (kCountBits * k);
+    if (threadIdx.x == 0) group_counts[blockIdx.x] = packed;
+}
+
+// Stable counting sort of a launch's tiles by cost key, highest key first.
+// A wave of k_tile_cost covers a group of kGroupTiles consecutive tiles and
+// counts their keys.  Here a 64-lane workgroup places 64 groups, a lane per
+// group: the lanes sum the counts of all groups (the totals) and of the
+// groups before the workgroup's first, a scan over the lanes adds the counts
+// of the lower lanes' groups, and each lane then writes its tiles' positions
+// in ascending tile order.  Small workgroups find free wave slots while a
+// render kernel occupies the device.
+constexpr int kOrderLoads = 16;                               // group counts in flight per lane
+__global__ __launch_bounds__(64) void k_tile_order(const uint8_t *__restrict__ keys,
+                                                   const uint32_t *__restrict__ group_counts, int n,
+                                                   int32_t *__restrict__ order) {
+    const int lane = (int)threadIdx.x;
+    const int ngroups = (n + kGroupTiles - 1) / kGroupTiles;
+    const int g0 = (int)blockIdx.x * 64;                      // first group of this workgroup
+    int total[kCostKeys], before[kCostKeys];
+#pragma unroll
+    for (int k = 0; k < kCostKeys; ++k) total[k] = before[k] = 0;
+    for (int base = 0; base < ngroups; base += 64 * kOrderLoads) {
+        uint32_t w[kOrderLoads];
+#pragma unroll
+        for (int u = 0; u < kOrderLoads; ++u) {
+            const int g = base + 64 * u + lane;
+            w[u] = g < ngroups ? group_counts[g] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kOrderLoads; ++u) {
+            const bool earlier = base + 64 * u + lane < g0;
+#pragma unroll
+            for (int k = 0; k < kCostKeys; ++k) {
+                const int c = (int)((w[u] >> (kCountBits * k)) & ((1u << kCountBits) - 1u));
+                total[k] += c;
+                before[k] += earlier ? c : 0;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kCostKeys; ++k) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            total[k] += __shfl_xor(total[k], off, 64);
+            before[k] += __shfl_xor(before[k], off, 64);
+        }
+    }
+    // this lane's group: its counts widened to kScanBits-bit fields and
+    // scanned over the lanes
+    const int g = g0 + lane;
+    const uint32_t mine = g < ngroups ? group_counts[g] : 0u;
+    uint64_t x = 0;
+#pragma unroll
+    for (int k = 0; k < kCostKeys; ++k)
+        x |= (uint64_t)((mine >> (kCountBits * k)) & ((1u << kCountBits) - 1u)) << (kScanBits * k);
+    uint64_t incl = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint64_t y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    const uint64_t excl = incl - x;
+    // first position of each key for this lane's tiles: all tiles of heavier
+    // keys, then those of the same key in earlier groups
+    int pos[kCostKeys];
+    int run = 0;
+#pragma unroll
+    for (int k = kCostKeys - 1; k >= 0; --k) {
+        pos[k] = run + before[k] + (int)((excl >> (kScanBits * k)) & ((1ull << kScanBits) - 1ull));
+        run += total[k];
+    }
+    if (g < ngroups) {
+        u32x4 kv[kGroupTiles / 16];
+#pragma unroll
+        for (int v = 0; v < kGroupTiles / 16; ++v)
+            kv[v] = *reinterpret_cast<const u32x4 *>(keys + kGroupTiles * g + 16 * v);
+#pragma unroll
+        for (int j = 0; j < kGroupTiles; ++j) {
+            const int i = kGroupTiles * g + j;
+            const int key = (int)byte_of(kv[j >> 4][(j >> 2) & 3], j & 3);
+            int at = pos[0];
+#pragma unroll
+            for (int k = 1; k < kCostKeys; ++k) at = key == k ? pos[k] : at;
+            if (i < n) order[at] = i;
+#pragma unroll
+            for (int k = 0; k < kCostKeys; ++k) pos[k] += key == k ? 1 : 0;
+        }
+    }
+}
+
+__global__ void k_identity_order(int32_t *__restrict__ order, int n) {
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) order[i] = i;
+}
+
 // Gather replay (measurement only): each lane re-issues, round by round, the
 // texel loads the renderer made for its pixel -- the brick slot, then the six
 // plane pairs and the four brick pairs -- with the same tile order and wave
@@ -923,8 +1114,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 // renderer's gathers alone can reach on this working set.
 __global__ __launch_bounds__(64) void k_gather_replay(const DevScene sc, const uint32_t *__restrict__ rec,
                                                       const int32_t *__restrict__ rec_count, int cap,
-                                                      int total_tiles, float *__restrict__ out) {
-    const int tile = xcd_remap((int)blockIdx.x, total_tiles);
+                                                      const int32_t *__restrict__ order, int total_tiles,
+                                                      float *__restrict__ out) {
+    const int slot = xcd_remap((int)blockIdx.x, total_tiles);
+    int tile = order ? order[slot] : slot;
+    if ((unsigned)tile >= (unsigned)total_tiles) tile = slot;   // an order of another launch
     const uint32_t q = (uint32_t)tile * 64u + threadIdx.x;
     const size_t slots = (size_t)total_tiles * 64u;
     const int n = min(rec_count[q], cap);
@@ -998,11 +1192,27 @@ hipError_t launch_render(const DevScene &sc, const RenderBatch &rb, hipStream_t 
     return hipLaunchKernel(render_kernel(rb), render_grid(rb), dim3(kRenderBlock), args, 0, stream);
 }
 
+hipError_t launch_tile_order(const DevScene &sc, const RenderBatch &rb, uint8_t *keys, uint32_t *group_counts,
+                             int32_t *order, hipStream_t stream) {
+    if (rb.total_tiles <= 0 || rb.total_tiles > kOrderMaxTiles) return hipErrorInvalidValue;
+    const int groups = (rb.total_tiles + kGroupTiles - 1) / kGroupTiles;
+    hipLaunchKernelGGL(k_tile_cost, dim3((unsigned)groups), dim3(64), 0, stream, sc, rb, keys, group_counts);
+    hipLaunchKernelGGL(k_tile_order, dim3((unsigned)((groups + 63) / 64)), dim3(64), 0, stream, keys, group_counts,
+                       rb.total_tiles, order);
+    return hipGetLastError();
+}
+
+hipError_t launch_identity_order(int32_t *order, int n, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_identity_order, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, order, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_gather_replay(const DevScene &sc, const uint32_t *rec, const int32_t *rec_count, int cap,
-                                int total_tiles, float *out, hipStream_t stream) {
+                                const int32_t *order, int total_tiles, float *out, hipStream_t stream) {
     if (total_tiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_gather_replay, dim3((unsigned)total_tiles), dim3(64), 0, stream, sc, rec, rec_count, cap,
-                       total_tiles, out);
+                       order, total_tiles, out);
     return hipGetLastError();
 }
 

@@ -49,7 +49,7 @@ class merf_camera(C.Structure):
 class merf_render_params(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("step", C.c_float), ("t_min", C.c_float),
                 ("delta_mode", C.c_int32), ("mlp_prec", C.c_int32), ("feat_prec", C.c_int32),
-                ("skip_mode", C.c_int32), ("stats_dev", C.c_void_p)]
+                ("skip_mode", C.c_int32), ("tile_order", C.c_int32), ("stats_dev", C.c_void_p)]
 
 
 EXPORTS = ["merf_scene_upload", "merf_render", "merf_free", "merf_last_error", "merf_set_hbm_budget",
@@ -181,16 +181,19 @@ def camera_array(cams):
 
 
 SKIP = {"distance": 0, "levels": 1}
+ORDER = {"heavy_first": 0, "plain": 1}
 
 
 def render_params(step: float = 0.0, t_min: float = 2e-4, delta_mode: int = 0, mlp_prec="f32",
-                  feat_prec="f32", skip="distance", stats_ptr: Optional[int] = None) -> merf_render_params:
+                  feat_prec="f32", skip="distance", order="heavy_first",
+                  stats_ptr: Optional[int] = None) -> merf_render_params:
     p = merf_render_params()
     p.struct_size = C.sizeof(merf_render_params)
     p.step, p.t_min, p.delta_mode = float(step), float(t_min), int(delta_mode)
     p.mlp_prec = PREC[mlp_prec] if isinstance(mlp_prec, str) else int(mlp_prec)
     p.feat_prec = PREC[feat_prec] if isinstance(feat_prec, str) else int(feat_prec)
     p.skip_mode = SKIP[skip] if isinstance(skip, str) else int(skip)
+    p.tile_order = ORDER[order] if isinstance(order, str) else int(order)
     p.stats_dev = stats_ptr
     return p
 
@@ -313,7 +316,7 @@ def _serve_lib():
     return lib
 
 
-MEASURE_EXPORTS = ["merf_gather_slots", "merf_record_gathers", "merf_replay_gathers"]
+MEASURE_EXPORTS = ["merf_gather_slots", "merf_record_gathers", "merf_render_timed", "merf_replay_gathers"]
 
 
 def _measure_lib():
@@ -323,12 +326,34 @@ def _measure_lib():
     vp, i32 = C.c_void_p, C.c_int32
     lib.merf_gather_slots.argtypes = [C.POINTER(merf_camera), i32, C.POINTER(i32)]
     lib.merf_record_gathers.argtypes = [vp, C.POINTER(merf_camera), i32, C.POINTER(merf_render_params), vp, i32, vp,
-                                        vp, vp]
-    lib.merf_replay_gathers.argtypes = [vp, vp, vp, i32, i32, vp, vp]
+                                        vp, vp, vp]
+    lib.merf_replay_gathers.argtypes = [vp, vp, vp, i32, vp, i32, vp, vp]
+    lib.merf_render_timed.argtypes = [vp, C.POINTER(merf_camera), i32, C.POINTER(merf_render_params), vp, vp, vp, vp]
     for n in MEASURE_EXPORTS:
         getattr(lib, n).restype = C.c_int
     lib._measure_ready = True
     return lib
+
+
+def _event_handle(e) -> int:
+    """Raw hipEvent_t of a torch.cuda.Event (recorded once, so that it exists),
+    a ctypes.c_void_p or an int."""
+    if hasattr(e, "cuda_event"):
+        assert e.cuda_event, "record the torch event once first"
+        return int(e.cuda_event)
+    return int(e.value) if isinstance(e, C.c_void_p) else int(e)
+
+
+def render_timed(handle: int, cams, out, ev_start, ev_end, stream=None, **params):
+    """merf_render_timed: render cams (one launch) into the cuda tensor out and
+    record the events ev_start / ev_end (timing enabled) right around the
+    render kernel."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    p = render_params(**params)
+    _check(_measure_lib().merf_render_timed(C.c_void_p(handle), camera_array(cams), len(cams), C.byref(p),
+                                            C.c_void_p(out.data_ptr()), C.c_void_p(_event_handle(ev_start)),
+                                            C.c_void_p(_event_handle(ev_end)), C.c_void_p(st.cuda_stream)))
 
 
 class GatherRecord:
@@ -345,20 +370,22 @@ class GatherRecord:
         self.n_slots = n.value
         self.rec = torch.empty((self.cap, self.n_slots, 4), dtype=torch.int32, device="cuda")
         self.count = torch.empty(self.n_slots, dtype=torch.int32, device="cuda")
+        self.order = torch.empty(self.n_slots // 64, dtype=torch.int32, device="cuda")
         self.stats = torch.zeros(8, dtype=torch.int64, device="cuda")
         self.image = torch.empty((cams.num_pixels(), 4), dtype=torch.float32, device="cuda")
         self.out = torch.empty((self.n_slots, 4), dtype=torch.float32, device="cuda")
         p = render_params(stats_ptr=self.stats.data_ptr(), **params)
         st = torch.cuda.current_stream().cuda_stream
         _check(lib.merf_record_gathers(C.c_void_p(handle), arr, len(cams), C.byref(p), C.c_void_p(self.rec.data_ptr()),
-                                       self.cap, C.c_void_p(self.count.data_ptr()), C.c_void_p(self.image.data_ptr()),
-                                       C.c_void_p(st)))
+                                       self.cap, C.c_void_p(self.count.data_ptr()), C.c_void_p(self.order.data_ptr()),
+                                       C.c_void_p(self.image.data_ptr()), C.c_void_p(st)))
 
     def replay(self, stream=None):
         import torch
         st = stream if stream is not None else torch.cuda.current_stream()
         _check(_measure_lib().merf_replay_gathers(C.c_void_p(self.handle), C.c_void_p(self.rec.data_ptr()),
-                                                   C.c_void_p(self.count.data_ptr()), self.cap, self.n_slots,
+                                                   C.c_void_p(self.count.data_ptr()), self.cap,
+                                                   C.c_void_p(self.order.data_ptr()), self.n_slots,
                                                    C.c_void_p(self.out.data_ptr()), C.c_void_p(st.cuda_stream)))
         return self.out
 

@@ -50,8 +50,8 @@ def test_gather_slots_and_measure_argument_checks():
     p = merf.render_params(stats_ptr=16)
     bogus = C.c_void_p(0x1234)
     assert lib.merf_record_gathers(bogus, merf.camera_array(cams), 1, C.byref(p), C.c_void_p(16), 8,
-                                   C.c_void_p(16), C.c_void_p(16), None) == merf.MERF_E_INVALID
-    assert lib.merf_replay_gathers(bogus, C.c_void_p(16), C.c_void_p(16), 8, 64, C.c_void_p(16),
+                                   C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), None) == merf.MERF_E_INVALID
+    assert lib.merf_replay_gathers(bogus, C.c_void_p(16), C.c_void_p(16), 8, C.c_void_p(16), 64, C.c_void_p(16),
                                    None) == merf.MERF_E_INVALID
 
 

@@ -52,3 +52,34 @@ def test_record_and_replay(torch, merf, tiny_scene, cap):
         assert (grid >> 13).max() < nbl ** 3 and (grid & 8191).max() < 9 * 9 * 9 * 8
     finally:
         r.close()
+
+
+def test_record_full_view_heavy_first_order(torch, merf):
+    print("gather record, full 1080p view: tile order is a permutation, heavy tiles first, replay in that order",
+          flush=True)
+    scene = synth.preset_scene("full")
+    cams = synth.full_camera()
+    r = merf.Renderer(scene)
+    try:
+        plain = r.render(cams, order="plain")
+        rec = merf.GatherRecord(r.handle, cams, cap=1)
+        out = rec.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(rec.image, plain)
+        tiles = rec.n_slots // 64
+        order = rec.order.cpu().numpy()
+        assert np.array_equal(np.sort(order), np.arange(tiles))
+        work = rec.count.cpu().numpy().reshape(tiles, 64).sum(1)[order]
+        # the tiles run first carry far more samples than those run last
+        head, tail = work[: tiles // 10].mean(), work[tiles // 2:].mean()
+        print(f"  evaluated samples per tile: first 10% {head:.1f}, last 50% {tail:.1f}", flush=True)
+        assert head > 4 * tail
+        count = rec.count.cpu().numpy()
+        assert np.array_equal(out[:, 0].cpu().numpy(), np.minimum(count, 1).astype(np.float32))
+        # the plain order records the identity
+        rec2 = merf.GatherRecord(r.handle, cams, cap=1, order="plain")
+        torch.cuda.synchronize()
+        assert np.array_equal(rec2.order.cpu().numpy(), np.arange(tiles))
+        assert torch.equal(rec2.count, rec.count)
+    finally:
+        r.close()

@@ -249,6 +249,50 @@ def test_full_1080p_parity_sampled_rows(torch, merf, full_scene):
     # the paper's level-by-level skipping gives the same image
     lv = gpu_render(torch, merf, full_scene, cams, skip="levels")
     assert np.array_equal(gpu, lv)
+    # so does the plain tile order (the default runs the 32400 tiles
+    # estimated heaviest first)
+    pl = gpu_render(torch, merf, full_scene, cams, order="plain")
+    assert np.array_equal(gpu, pl)
+
+
+def test_tile_order_multi_camera_same_image(torch, merf, full_scene):
+    say("full scene, 3 orbit views at 1280x720 in one launch (43200 tiles): heavy-first vs plain order")
+    cams = synth.orbit_cameras(3, w=1280, h=720)
+    a = gpu_render(torch, merf, full_scene, cams)
+    b = gpu_render(torch, merf, full_scene, cams, order="plain")
+    assert np.array_equal(a, b)
+    # one camera alone (14400 tiles, ordered on its own) gives the same bits
+    one = gpu_render(torch, merf, full_scene, cams.subset(1))
+    n = 1280 * 720
+    assert np.array_equal(one, a[n:2 * n])
+
+
+def test_tile_order_concurrent_streams(torch, merf, full_scene):
+    say("full 1080p view rendered 12 times on 3 streams at once (tile-order work buffers shared and reused)")
+    cams = synth.full_camera()
+    r = merf.Renderer(full_scene)
+    try:
+        ref = r.render(cams, order="plain")
+        streams = [torch.cuda.Stream() for _ in range(3)]
+        outs = [torch.empty_like(ref) for _ in range(12)]
+        torch.cuda.synchronize()
+        for i, o in enumerate(outs):
+            r.render(cams, out=o, stream=streams[i % 3])
+        torch.cuda.synchronize()
+        for o in outs:
+            assert torch.equal(o, ref)
+    finally:
+        r.close()
+
+
+def test_tile_order_rejects_unknown_value(torch, merf, tiny_scene, tiny_cams):
+    r = merf.Renderer(tiny_scene)
+    try:
+        with pytest.raises(merf.MerfError) as e:
+            r.render(tiny_cams, order=2)
+        assert e.value.code == merf.MERF_E_INVALID
+    finally:
+        r.close()
 
 
 def test_full_scene_orbit_views_sampled(torch, merf, full_scene):
