@@ -423,6 +423,9 @@ def main():
                     help="requests in the serving-mix leg (0 skips it)")
     ap.add_argument("--no-overlap", action="store_true",
                     help="skip the two-frames-in-flight leg (its concurrent launches would blur per-kernel profiles)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time only the headline frames (for profiling: the other legs launch the same render "
+                         "kernel with other settings, which would mix into its per-kernel averages)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after timing, run a plain device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
@@ -508,7 +511,7 @@ def main():
                      "traffic": traffic},
         "kernel_ms": kernel_ms,
         "frame_gpu_ms": float(frame.mean()),
-        "latency_ms": isolated_latency(r, cams, out, 100),
+        "latency_ms": None if args.headline_only else isolated_latency(r, cams, out, 100),
         "per_ray": {"evaluated": evaluated / n_rays, "contributing": contributing / n_rays,
                     "visited": visited / n_rays, "occ_lookups": occ_lookups / n_rays},
         "alg_bytes_per_launch": alg_bytes,
@@ -517,59 +520,60 @@ def main():
     # double-buffers): the tail of one frame overlaps the start of the next
     if not args.no_overlap:
         res["two_in_flight"] = two_in_flight(r, cams, out, args.steps)
-    # the same frame with the tiles in plain order (no cost prepass)
-    pl_img = torch.empty_like(out)
-    pl_kernel, pl_frame = timed_frames(merf, r, cams, pl_img, 20, order="plain")
-    res["plain_order"] = {"kernel_ms": pl_kernel, "frame_gpu_ms": pl_frame,
-                          "Mrays/s": rays / (pl_frame * 1e-3) / 1e6,
-                          "latency_ms": isolated_latency(r, cams, pl_img, 100, order="plain"),
-                          "same_image": bool(torch.equal(pl_img, out))}
-    del pl_img
-    # the paper's level-by-level skipping (skip_mode 1) on the same frame:
-    # same image, more march steps
-    lv_img = torch.empty_like(out)
-    st_lv = torch.zeros(8, dtype=torch.int64, device="cuda")
-    r.render(cams, out=lv_img, stats=st_lv, skip="levels")
-    lv_kernel, lv_ms = timed_frames(merf, r, cams, lv_img, 20, skip="levels")
-    c_lv = st_lv.cpu().numpy()
-    res["skip_levels"] = {"kernel_ms": lv_kernel, "frame_gpu_ms": lv_ms, "Mrays/s": rays / (lv_ms * 1e-3) / 1e6,
-                          "visited_per_ray": float(c_lv[2]) / n_rays, "occ_lookups_per_ray": float(c_lv[1]) / n_rays,
-                          "same_image": bool(torch.equal(lv_img, out))}
-    del lv_img
-    # gather bound: replay the frame's recorded texel loads with no arithmetic
-    rec = merf.GatherRecord(r.handle, cams, cap=96)
-    torch.cuda.synchronize()
-    counts = rec.count.cpu().numpy()
-    for _ in range(3):
-        rec.replay()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(20):
-        rec.replay()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    rp_ms = e0.elapsed_time(e1) / 20
-    gather_bytes = evaluated * B_EVAL + contributing * B_CONTRIB + n_rays * B_RAY
-    res["gather_replay"] = {"kernel_ms": rp_ms, "gather_bytes": gather_bytes,
-                            "replay_GB/s": gather_bytes / (rp_ms * 1e-3) / 1e9,
-                            "render_GB/s": gather_bytes / (kernel_ms * 1e-3) / 1e9,
-                            "render_frac_of_replay": rp_ms / kernel_ms,
-                            "frame_frac_of_replay": rp_ms / float(frame.mean()),
-                            "max_samples_per_ray": int(counts.max()),
-                            "unrecorded_samples": int(np.maximum(counts - rec.cap, 0).sum()),
-                            "same_image": bool(torch.equal(rec.image, out))}
-    del rec
-    # precision variants of the deferred MLP (fp16 / bf16 inputs on MFMA,
-    # fp32 accumulation); compositing and transmittance stay fp32
     prec = {}
-    for name, mlp, feat in (("mlp_f16", "f16", "f32"), ("mlp_bf16", "bf16", "f32"),
-                            ("feat_f16_mlp_f16", "f16", "f16"), ("feat_f16_mlp_bf16", "bf16", "f16")):
-        img = torch.empty_like(out)
-        k_ms, ms = timed_frames(merf, r, cams, img, 20, mlp_prec=mlp, feat_prec=feat)
-        prec[name] = {"mlp": mlp, "features": feat, "kernel_ms": k_ms, "frame_gpu_ms": ms,
-                      "Mrays/s": rays / (ms * 1e-3) / 1e6, "_img": img}
-    res["precision"] = prec
+    if not args.headline_only:
+        # the same frame with the tiles in plain order (no cost prepass)
+        pl_img = torch.empty_like(out)
+        pl_kernel, pl_frame = timed_frames(merf, r, cams, pl_img, 20, order="plain")
+        res["plain_order"] = {"kernel_ms": pl_kernel, "frame_gpu_ms": pl_frame,
+                              "Mrays/s": rays / (pl_frame * 1e-3) / 1e6,
+                              "latency_ms": isolated_latency(r, cams, pl_img, 100, order="plain"),
+                              "same_image": bool(torch.equal(pl_img, out))}
+        del pl_img
+        # the paper's level-by-level skipping (skip_mode 1) on the same frame:
+        # same image, more march steps
+        lv_img = torch.empty_like(out)
+        st_lv = torch.zeros(8, dtype=torch.int64, device="cuda")
+        r.render(cams, out=lv_img, stats=st_lv, skip="levels")
+        lv_kernel, lv_ms = timed_frames(merf, r, cams, lv_img, 20, skip="levels")
+        c_lv = st_lv.cpu().numpy()
+        res["skip_levels"] = {"kernel_ms": lv_kernel, "frame_gpu_ms": lv_ms, "Mrays/s": rays / (lv_ms * 1e-3) / 1e6,
+                              "visited_per_ray": float(c_lv[2]) / n_rays, "occ_lookups_per_ray": float(c_lv[1]) / n_rays,
+                              "same_image": bool(torch.equal(lv_img, out))}
+        del lv_img
+        # gather bound: replay the frame's recorded texel loads with no arithmetic
+        rec = merf.GatherRecord(r.handle, cams, cap=96)
+        torch.cuda.synchronize()
+        counts = rec.count.cpu().numpy()
+        for _ in range(3):
+            rec.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(20):
+            rec.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        rp_ms = e0.elapsed_time(e1) / 20
+        gather_bytes = evaluated * B_EVAL + contributing * B_CONTRIB + n_rays * B_RAY
+        res["gather_replay"] = {"kernel_ms": rp_ms, "gather_bytes": gather_bytes,
+                                "replay_GB/s": gather_bytes / (rp_ms * 1e-3) / 1e9,
+                                "render_GB/s": gather_bytes / (kernel_ms * 1e-3) / 1e9,
+                                "render_frac_of_replay": rp_ms / kernel_ms,
+                                "frame_frac_of_replay": rp_ms / float(frame.mean()),
+                                "max_samples_per_ray": int(counts.max()),
+                                "unrecorded_samples": int(np.maximum(counts - rec.cap, 0).sum()),
+                                "same_image": bool(torch.equal(rec.image, out))}
+        del rec
+        # precision variants of the deferred MLP (fp16 / bf16 inputs on MFMA,
+        # fp32 accumulation); compositing and transmittance stay fp32
+        for name, mlp, feat in (("mlp_f16", "f16", "f32"), ("mlp_bf16", "bf16", "f32"),
+                                ("feat_f16_mlp_f16", "f16", "f16"), ("feat_f16_mlp_bf16", "bf16", "f16")):
+            img = torch.empty_like(out)
+            k_ms, ms = timed_frames(merf, r, cams, img, 20, mlp_prec=mlp, feat_prec=feat)
+            prec[name] = {"mlp": mlp, "features": feat, "kernel_ms": k_ms, "frame_gpu_ms": ms,
+                          "Mrays/s": rays / (ms * 1e-3) / 1e6, "_img": img}
+        res["precision"] = prec
     if args.copy_probe_mb > 0:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters read
         # exactly copy_probe_mb MiB each when the counters are exact
