@@ -12,8 +12,8 @@ one stream; inputs are resident in device memory before timing starts.
 
 Prints ONE JSON line.  Besides throughput it reports:
   roofline      algorithmic gather bytes per launch / average render-kernel
-                time (HIP events recorded around that kernel on its stream),
-                against HBM peak;
+                time (HIP events recorded around that kernel on its stream,
+                on every fifth timed step), against HBM peak;
   latency_ms    p50 / p99 of frames rendered alone (host wall time from the
                 call until the frame is done, prepass included);
   cpu_baseline  the FP64 oracle on a bounded row sample of the same frame.
@@ -423,6 +423,8 @@ def main():
                     help="requests in the serving-mix leg (0 skips it)")
     ap.add_argument("--no-overlap", action="store_true",
                     help="skip the two-frames-in-flight leg (its concurrent launches would blur per-kernel profiles)")
+    ap.add_argument("--event-every", type=int, default=5,
+                    help="record the render kernel's timing events on every n-th timed step")
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the headline frames (for profiling: the other legs launch the same render "
                          "kernel with other settings, which would mix into its per-kernel averages)")
@@ -473,16 +475,27 @@ def main():
     # per step, the library records a pair of events right around the render
     # kernel on its stream (the frame's tile-order prepass runs before, on
     # the library's own stream, overlapping the previous frame)
-    tm = KernelTimer(args.steps)
+    # every event_every-th step records its events (an event record between
+    # two kernels costs a few microseconds, so timing every step would slow
+    # the very frames being measured)
+    ev_steps = list(range(0, args.steps, max(1, args.event_every)))
+    tm = KernelTimer(len(ev_steps))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    j = 0
     for i in range(args.steps):
-        merf.render_timed(r.handle, cams, out, *tm.pair(i))
+        if j < len(ev_steps) and i == ev_steps[j]:
+            merf.render_timed(r.handle, cams, out, *tm.pair(j))
+            j += 1
+        else:
+            r.render(cams, out=out)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    per = np.array([tm.ms(*tm.pair(i)) for i in range(args.steps)])        # ms, render kernel
-    # ms from one frame's end to the next one's: the GPU time per frame
-    frame = np.array([tm.ms(tm.pair(i - 1)[1], tm.pair(i)[1]) for i in range(1, args.steps)])
+    per = np.array([tm.ms(*tm.pair(j)) for j in range(len(ev_steps))])        # ms, render kernel
+    # GPU time per frame: from one timed frame's end to the next one's, over
+    # the frames between them
+    frame = np.array([tm.ms(tm.pair(j)[1], tm.pair(j + 1)[1]) / (ev_steps[j + 1] - ev_steps[j])
+                      for j in range(len(ev_steps) - 1)] or [float("nan")])
     tm.close()
 
     ms_per_step = wall * 1e3 / args.steps

@@ -122,10 +122,11 @@ typedef struct {
                                              heaviest first for launches of 8192 to
                                              131072 tiles (a prepass marches 4 rays of
                                              each tile to their first occupied sample;
-                                             the first calls on a device allocate up to
-                                             8 work buffers of 640 KB, kept until the
-                                             process ends), plain order otherwise;
-                                             1 = plain order */
+                                             calls on a device allocate up to 64 work
+                                             buffers of 672 KB, kept until the process
+                                             ends; with all 64 in flight, a call waits
+                                             for the oldest to finish), plain order
+                                             otherwise; 1 = plain order */
     uint64_t *stats_dev;                  /* NULL, or device uint64[8] to which the render
                                              ADDS: [0] rays, [1] occupancy lookups
                                              (skip_mode 0: distance-grid lookups),

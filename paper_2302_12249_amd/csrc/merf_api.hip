@@ -206,15 +206,17 @@ size_t scene_device_bytes(const merf_scene_desc *desc) {
 
 namespace {
 
-// Work buffers of the tile order (cost keys and order of up to
-// kOrderMaxTiles tiles).  The prepass runs on a stream of the library's own
-// (one per device), since it reads only the resident scene and these
-// buffers: it need not wait for the caller's earlier work, so it overlaps
-// the previous frame's render.  The caller's stream waits for its event
-// `ready`.  A buffer is free again once the event `done`, recorded after the
-// render that read it, has completed; a device has at most kOrderBufs, after
-// which the prepass waits (on the device) for the buffer used longest ago.
-// Buffers and streams are held until the process ends.
+// Work buffers of the tile order (cost keys, their group counts and the
+// order, for up to kOrderMaxTiles tiles).  The prepass runs on a stream of
+// the library's own (one per device), since it reads only the resident scene
+// and these buffers: it need not wait for the caller's earlier work, so it
+// overlaps the previous frame's render.  The caller's stream waits for its
+// event `ready`.  A buffer is free again once the event `done`, recorded
+// after the render that read it, has completed; the host checks that, so no
+// device queue ever waits on the caller's stream (a device-side wait there
+// cost about 10 us per frame).  A device has at most kOrderBufs buffers; when
+// all are in flight, the call waits on the host for the oldest.  Buffers and
+// streams are held until the process ends.
 struct OrderBuf {
     int device;
     uint8_t *keys;
@@ -223,7 +225,7 @@ struct OrderBuf {
     hipEvent_t ready, done;
     uint64_t last_use;                           // 0: not used yet
 };
-constexpr int kOrderBufs = 8;
+constexpr int kOrderBufs = 64;
 // The events order device work only (the host merely asks whether a buffer
 // is free), so they skip the system-scope cache flush of an event record.
 constexpr unsigned kOrderEventFlags = hipEventDisableTiming | hipEventDisableSystemFence;
@@ -242,9 +244,8 @@ hipStream_t order_stream(int device) {
     return st;
 }
 
-// Index of a buffer the prepass on stream may use, or -1 (caller holds
-// g_order_mutex).
-int order_buffer(int device, hipStream_t stream) {
+// Index of a free buffer of the device, or -1 (caller holds g_order_mutex).
+int order_buffer(int device) {
     int oldest = -1, n = 0;
     for (int i = 0; i < (int)g_order_bufs.size(); ++i) {
         const OrderBuf &b = g_order_bufs[i];
@@ -268,7 +269,7 @@ int order_buffer(int device, hipStream_t stream) {
         if (b.order) (void)hipFree(b.order);
         if (b.ready) (void)hipEventDestroy(b.ready);
     }
-    if (oldest >= 0 && hipStreamWaitEvent(stream, g_order_bufs[oldest].done, 0) == hipSuccess) return oldest;
+    if (oldest >= 0 && hipEventSynchronize(g_order_bufs[oldest].done) == hipSuccess) return oldest;
     return -1;
 }
 
@@ -286,9 +287,14 @@ int render_launch(const DevScene &ds, RenderBatch &rb, int tile_order, hipStream
     if (tile_order == 0 && rb.total_tiles >= kOrderMinTiles && rb.total_tiles <= kOrderMaxTiles &&
         !capturing(stream)) {
         lock.lock();
-        int device = 0;
-        hipStream_t ps = hipGetDevice(&device) == hipSuccess ? order_stream(device) : nullptr;
-        if (ps) buf = order_buffer(device, ps);
+        // the work buffers are allocated on the current device: order only
+        // when the stream belongs to it
+        int device = -1;
+        hipDevice_t sdev = -1;
+        const bool same = hipGetDevice(&device) == hipSuccess &&
+                          (!stream || (hipStreamGetDevice(stream, &sdev) == hipSuccess && sdev == device));
+        hipStream_t ps = same ? order_stream(device) : nullptr;
+        if (ps) buf = order_buffer(device);
         (void)hipGetLastError();              // a not-ready event query is no error
         if (buf >= 0) {
             const OrderBuf &b = g_order_bufs[buf];

@@ -963,7 +963,7 @@ constexpr int kCostSteps = 64;
 constexpr int kGroupTiles = 64 / kCostRays;                   // tiles of one k_tile_cost wave
 constexpr int kCountBits = kGroupTiles < 32 ? 5 : 7;           // a group's count of one key
 constexpr int kScanBits = 64 / kCostKeys;                      // a workgroup's count of one key
-static_assert(kCostKeys * kCountBits <= 32 && 64 * kGroupTiles < (1 << kScanBits), "count fields");
+static_assert(kCostKeys * kCountBits <= 32 && (uint64_t)64 * kGroupTiles < (1ull << kScanBits), "count fields");
 __global__ __launch_bounds__(64) void k_tile_cost(const DevScene sc, const RenderBatch rb, uint8_t *__restrict__ keys,
                                                   uint32_t *__restrict__ group_counts) {
     const int g = (int)blockIdx.x * 64 + (int)threadIdx.x;
