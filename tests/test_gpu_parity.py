@@ -285,6 +285,33 @@ def test_tile_order_concurrent_streams(torch, merf, full_scene):
         r.close()
 
 
+def test_tile_order_many_frames_in_flight(torch, merf, full_scene):
+    say("full 1080p view rendered 80 times back to back without waiting (more frames in flight than "
+        "tile-order work buffers, so buffers are reused and the host waits for the oldest)")
+    cams = synth.full_camera()
+    r = merf.Renderer(full_scene)
+    try:
+        ref = r.render(cams, order="plain")
+        outs = [torch.empty_like(ref) for _ in range(80)]
+        torch.cuda.synchronize()
+        for o in outs:
+            r.render(cams, out=o)
+        torch.cuda.synchronize()
+        for o in outs:
+            assert torch.equal(o, ref)
+    finally:
+        r.close()
+
+
+def test_tile_order_4k_frame(torch, merf, full_scene):
+    say("full scene, one 3840x2160 view (129600 tiles, the largest ordered launch size range)")
+    cams = synth.make_cameras([synth.full_camera().c2w[0].astype(np.float64)], [(3840, 2160)])
+    a = gpu_render(torch, merf, full_scene, cams)
+    b = gpu_render(torch, merf, full_scene, cams, order="plain")
+    assert np.array_equal(a, b)
+    assert a[:, 3].max() > 0.5
+
+
 def test_tile_order_rejects_unknown_value(torch, merf, tiny_scene, tiny_cams):
     r = merf.Renderer(tiny_scene)
     try:
