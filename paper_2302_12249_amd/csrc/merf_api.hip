@@ -295,7 +295,8 @@ int render_launch(const DevScene &ds, RenderBatch &rb, int tile_order, hipStream
                           (!stream || (hipStreamGetDevice(stream, &sdev) == hipSuccess && sdev == device));
         hipStream_t ps = same ? order_stream(device) : nullptr;
         if (ps) buf = order_buffer(device);
-        (void)hipGetLastError();              // a not-ready event query is no error
+        // a not-ready event query is no error (leave any other error alone)
+        if (hipPeekAtLastError() == hipErrorNotReady) (void)hipGetLastError();
         if (buf >= 0) {
             const OrderBuf &b = g_order_bufs[buf];
             hipError_t e = launch_tile_order(ds, rb, b.keys, b.group_counts, b.order, ps);
@@ -309,21 +310,30 @@ int render_launch(const DevScene &ds, RenderBatch &rb, int tile_order, hipStream
     if (e != hipSuccess) return hip_fail(e, "start event");
     e = launch_render(ds, rb, stream);
     if (e != hipSuccess) return hip_fail(e, "render launch");
-    e = ev_end ? hipEventRecord(ev_end, stream) : hipSuccess;
-    if (e != hipSuccess) return hip_fail(e, "end event");
-    if (order_out) {
+    const char *what = nullptr;
+    if (ev_end && (e = hipEventRecord(ev_end, stream)) != hipSuccess) what = "end event";
+    if (!what && order_out) {
         e = rb.order ? hipMemcpyAsync(order_out, rb.order, sizeof(int32_t) * (size_t)rb.total_tiles,
                                       hipMemcpyDeviceToDevice, stream)
                      : launch_identity_order(order_out, rb.total_tiles, stream);
-        if (e != hipSuccess) return hip_fail(e, "tile order copy");
+        if (e != hipSuccess) what = "tile order copy";
     }
     if (buf >= 0) {
+        // after everything that reads the buffer on this stream, errors or not
         OrderBuf &b = g_order_bufs[buf];
-        e = hipEventRecord(b.done, stream);
-        if (e != hipSuccess) return hip_fail(e, "tile order event");
-        b.last_use = ++g_order_uses;
+        const hipError_t ed = hipEventRecord(b.done, stream);
+        if (ed == hipSuccess) {
+            b.last_use = ++g_order_uses;
+        } else {
+            // without its event the buffer cannot be known free again
+            b.device = -1;
+            if (!what) {
+                e = ed;
+                what = "tile order event";
+            }
+        }
     }
-    return MERF_OK;
+    return what ? hip_fail(e, what) : MERF_OK;
 }
 
 int check_params(const merf_render_params *p, int res, float *step_out) {
