@@ -39,6 +39,10 @@ B_EVAL, B_CONTRIB, B_OCC, B_RAY = 24, 140, 1, 16
 KERNEL_SOURCES = ["paper_2302_12249_amd/csrc/merf_render.hip", "paper_2302_12249_amd/csrc/merf_device.h",
                   "paper_2302_12249_amd/csrc/merf_api.hip", "paper_2302_12249_amd/csrc/merf_ingest.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_full_1080p_traffic.json")
+MFMA_FILE = os.path.join(ROOT, "profiles", "render_full_1080p_mfma.json")
+# the deferred MLP per pixel: 34 x 16 + 16 x 16 + 16 x 3 multiply-adds (App. B)
+MLP_FLOP_PER_PIXEL = 2 * (34 * 16 + 16 * 16 + 16 * 3)
+MFMA_F32_PEAK_TFLOPS = 157.3
 
 
 def kernel_hash():
@@ -46,6 +50,16 @@ def kernel_hash():
     for f in KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     return h.hexdigest()[:16]
+
+
+def measured_mfma():
+    """MFMA counters of the render kernel from the committed rocprofv3 run, if
+    taken on the current kernel source; otherwise None."""
+    try:
+        t = json.load(open(MFMA_FILE))
+    except (OSError, ValueError):
+        return None
+    return t if t.get("kernel_sha") == kernel_hash() else None
 
 
 def measured_traffic():
@@ -529,6 +543,14 @@ def main():
                     "visited": visited / n_rays, "occ_lookups": occ_lookups / n_rays},
         "alg_bytes_per_launch": alg_bytes,
     }
+    # the deferred MLP, the path's only dense contraction, on the matrix cores
+    mf = measured_mfma()
+    mlp_flop = n_rays * MLP_FLOP_PER_PIXEL
+    res["mlp_mfma"] = {"flop_per_launch": mlp_flop,
+                       "TFLOP/s_over_kernel": mlp_flop / (kernel_ms * 1e-3) / 1e12,
+                       "peak_TFLOP/s": MFMA_F32_PEAK_TFLOPS,
+                       "issued_flop_per_launch": mf["mfma_flop_per_launch"] if mf else None,
+                       "mfma_busy_pct": mf["mfma_util_pct"] if mf else None}
     # the same frames with two in flight (alternating streams, as a renderer
     # double-buffers): the tail of one frame overlaps the start of the next
     if not args.no_overlap:
