@@ -335,6 +335,42 @@ def variants_workload(steps: int):
             "variants": res}
 
 
+def resolutions_workload(steps: int):
+    """The Full scene from the full-size camera at several resolutions, frames
+    back to back on one stream, with the tiles heaviest first and in plain
+    order: where the tile order starts to pay (launches of 8192 tiles or more)."""
+    import torch
+    import synth
+    from paper_2302_12249_amd import merf
+
+    full = synth.preset_scene("full")
+    pose = synth.full_camera().c2w[0].astype("float64")
+    r = merf.Renderer(full)
+    res = {}
+    for w, h in ((256, 256), (512, 512), (1280, 720), (1920, 1080), (2560, 1440), (3840, 2160)):
+        cams = synth.make_cameras([pose], [(w, h)])
+        rays = cams.num_pixels()
+        out = torch.empty((rays, 4), dtype=torch.float32, device="cuda")
+        row = {"tiles": ((w + 7) // 8) * ((h + 7) // 8)}
+        for order in ("heavy_first", "plain"):
+            for _ in range(5):
+                r.render(cams, out=out, order=order)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                r.render(cams, out=out, order=order)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / steps
+            row[order] = {"ms_per_frame": ms, "Mrays/s": rays / (ms * 1e-3) / 1e6}
+        res[f"{w}x{h}"] = row
+        del out
+    r.close()
+    return {"metric": "Mrays/s by resolution, frames back to back", "value": res["1920x1080"]["heavy_first"]["Mrays/s"],
+            "unit": "Mrays/s", "n_gpus": 1, "steps": steps, "higher_is_better": True, "data": "synthetic",
+            "config": {"workload": "full-size scene and camera pose at six resolutions, both tile orders"},
+            "resolutions": res}
+
+
 class KernelTimer:
     """Pairs of HIP timing events created without the system-scope cache
     flush that an ordinary event record performs (hipEventDisableSystemFence):
@@ -429,9 +465,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["full", "precision", "stress", "variants"], default="full",
+    ap.add_argument("--workload", choices=["full", "precision", "stress", "variants", "resolutions"], default="full",
                     help="full (default, the headline line), precision (16 x 1080p views), stress, "
-                         "or variants (representations: memory against speed)")
+                         "variants (representations: memory against speed) or resolutions (tile order by frame size)")
     ap.add_argument("--stress-scenes", type=int, default=32)
     ap.add_argument("--serve-requests", type=int, default=240,
                     help="requests in the serving-mix leg (0 skips it)")
@@ -463,6 +499,9 @@ def main():
         return
     if args.workload == "variants":
         print(json.dumps(variants_workload(args.steps)), flush=True)
+        return
+    if args.workload == "resolutions":
+        print(json.dumps(resolutions_workload(args.steps)), flush=True)
         return
     if args.workload == "stress":
         print(json.dumps(stress_workload(args.stress_scenes, args.serve_requests)), flush=True)
