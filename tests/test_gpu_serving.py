@@ -65,10 +65,13 @@ def test_mix_equals_alone(torch, merf, scenes, use_graphs):
     srv = merf.Server(slots=3, max_batch=8, use_graphs=use_graphs)
     try:
         ids = [srv.add_scene(s) for s in scenes]
-        outs, tickets = [], []
+        # NaN-filled outputs, filled before any submit: the server's streams
+        # are not ordered after torch's, so a pending fill could land after
+        # the render
+        outs = [torch.full((int(w) * int(h), 4), float("nan"), device="cuda") for w, h in cams.size]
+        torch.cuda.synchronize()
+        tickets = []
         for i in range(len(cams)):
-            w, h = cams.size[i]
-            outs.append(torch.full((int(w) * int(h), 4), float("nan"), device="cuda"))
             p = merf.render_params(mlp_prec=prec[i])
             tickets.append(srv.submit(ids[scene_of[i]], arr, i, outs[i].data_ptr(), p))
         lats = [srv.wait(t)[0] for t in tickets]
