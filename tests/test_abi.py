@@ -53,6 +53,8 @@ def test_gather_slots_and_measure_argument_checks():
                                    C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), None) == merf.MERF_E_INVALID
     assert lib.merf_replay_gathers(bogus, C.c_void_p(16), C.c_void_p(16), 8, C.c_void_p(16), 64, C.c_void_p(16),
                                    None) == merf.MERF_E_INVALID
+    assert lib.merf_render_timed(bogus, merf.camera_array(cams), 1, C.byref(p), C.c_void_p(16), C.c_void_p(16),
+                                 C.c_void_p(16), None) == merf.MERF_E_INVALID
 
 
 @pytest.mark.parametrize("field,value", [("slots", 0), ("slots", 9), ("max_batch", 0), ("max_batch", 17),
