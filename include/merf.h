@@ -119,7 +119,7 @@ typedef struct {
                                              leaving one empty cell per step (Sec. 6) */
     int32_t tile_order;                   /* order in which the 8x8 tiles of a launch run,
                                              same image either way: 0 = estimated
-                                             heaviest first for launches of 8192 to
+                                             heaviest first for launches of 6144 to
                                              131072 tiles (a prepass marches 4 rays of
                                              each tile to their first occupied sample;
                                              calls on a device allocate up to 64 work

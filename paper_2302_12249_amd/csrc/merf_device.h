@@ -23,11 +23,12 @@ constexpr int kMaxDistRes = 1024;                // finest occupancy resolution 
 constexpr int kOctMaxRes = 256;                  // up to this r_f the grid has eight octant forms
 // Tile order of a launch: a prepass estimates each tile's cost from
 // kCostRays of its rays, and the tiles run heaviest first.  Launches of fewer
-// than kOrderMinTiles tiles (all of them start at once on 256 CUs) or more
-// than kOrderMaxTiles (one workgroup sorts the keys) keep the plain order.
+// than kOrderMinTiles tiles (1.5 waves per wave slot of the device; measured
+// to gain nothing below) or more than kOrderMaxTiles (the work buffers' size;
+// there the end of the launch is a small part of it) keep the plain order.
 constexpr int kCostRays = 4;
 constexpr int kCostKeys = kCostRays + 1;         // key = rays of the tile that reach occupied space
-constexpr int kOrderMinTiles = 8192;
+constexpr int kOrderMinTiles = 6144;
 constexpr int kOrderMaxTiles = 1 << 17;
 
 // Scene as laid out in device memory.
