@@ -82,8 +82,9 @@ int merf_server_remove_scene(merf_server_t s, int32_t scene_id);
  * is caller-owned device memory of width * height * 4 floats that must stay
  * valid until the request completes.  The request runs on the server's own
  * streams, not ordered after any work of the caller: out_rgba_dev must have
- * no pending writes when submitted.  Errors: MERF_E_INVALID (unknown scene,
- * bad camera or parameters, NULL output). */
+ * no pending writes when submitted.  p->tile_order is ignored: served
+ * launches overlap one another and keep the plain tile order.  Errors:
+ * MERF_E_INVALID (unknown scene, bad camera or parameters, NULL output). */
 int merf_server_submit(merf_server_t s, int32_t scene_id, const merf_camera *cam, const merf_render_params *p,
                        float *out_rgba_dev, uint64_t *ticket);
 
