@@ -34,6 +34,22 @@ METRIC = "rays/sec (Mrays/s) at 1080p, % HBM roofline; p50/p99 frame latency ser
 # 4 B brick index; per sample with alpha != 0 another 20 x 7 appearance codes;
 # 1 B per occupancy lookup; 16 B of output per ray.
 B_EVAL, B_CONTRIB, B_OCC, B_RAY = 24, 140, 1, 16
+# algorithmic vector-ALU FLOPs (the method's arithmetic as the oracle states
+# it, counting a multiply-add as 2 and a transcendental as 1):
+#   evaluated sample: interpolation weights (grid 8 triple products + 3
+#     complements = 19; planes 3 x (4 products + 2 complements) = 18), the
+#     density sum over 20 texels (40), Eq. 8 affine (2), exp (1), alpha and
+#     transmittance update (5)                                     = 85
+#   sample with alpha != 0: 7 channels x 20 texels (280), Eq. 8 affine (14),
+#     7 sigmoids (21), compositing 7 multiply-adds (14)              = 329
+#   ray: pinhole direction and normalisation (20), direction encoding (36),
+#     RGB = C_d + h (3)                                              = 59
+# The deferred MLP (1696 FLOP per pixel) runs on the matrix cores and is
+# reported separately (mlp_mfma).
+F_EVAL, F_CONTRIB, F_RAY = 85, 329, 59
+# vector FP32 peak without packed-FP32 instructions, derived from the unit
+# counts: 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP (FMA) x 2.4 GHz
+VALU_F32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # everything that decides what the render kernel reads and how (kernel, scene
 # layout, brick packing); counters taken on other sources are stale
 KERNEL_SOURCES = ["paper_2302_12249_amd/csrc/merf_render.hip", "paper_2302_12249_amd/csrc/merf_device.h",
@@ -72,6 +88,24 @@ def measured_traffic():
     if t.get("kernel_sha") != kernel_hash():
         return None
     return t.get("bytes_per_launch")
+
+
+def phase_profile(merf, r, cams, out):
+    """Shader-clock cycles per wave by phase, and loop counts per wave, of one
+    frame (merf_render_phases: the counting kernel with clock reads at points
+    all 64 lanes pass together; same image)."""
+    ph = merf.render_phases(r.handle, cams, out)
+    waves = max(ph["waves"], 1)
+    names = ["setup", "march", "open", "shade", "composite", "mlp"]
+    cyc = {n: ph[n + "_cycles"] / waves for n in names}
+    total = sum(cyc.values())
+    return {"cycles_per_wave": cyc, "total_cycles_per_wave": total,
+            "fraction": {n: cyc[n] / total for n in names},
+            "per_wave": {"march_passes": ph["march_passes"] / waves, "open_passes": ph["open_passes"] / waves,
+                         "shade_passes": ph["shade_passes"] / waves, "rounds": ph["rounds"] / waves},
+            "shade_lane_util": ph["shade_lanes"] / max(64 * ph["shade_passes"], 1),
+            "opens_per_ray": ph["open_lanes"] / max(ph["stats"]["rays"], 1),
+            "waves": ph["waves"]}
 
 
 def cpu_model() -> str:
@@ -177,24 +211,28 @@ def serving_leg(n_requests: int, seed: int = 200):
             "graph_launches": int(st["graph_launches"]), "max_inflight": int(st["max_inflight"])}
 
 
-def precision_workload(steps: int):
+def precision_config(steps: int, scene=None):
     """Precision config: the full-size scene as 16 seeded 1920x1080 orbit views in
     one batched render call; fp32 / fp16 / bf16 MLP and fp16 features, each
-    against the FP64 oracle on every 64th row of every view."""
+    timed (CUDA events around `steps` calls) and compared with the FP64 oracle
+    on every 64th row of every view (PSNR over all sampled pixels, max error
+    over the pixels the oracle does not flag as fragile)."""
     import numpy as np
     import torch
     import oracle
     import synth
     from paper_2302_12249_amd import merf
 
-    scene = synth.preset_scene("full")
+    scene = scene if scene is not None else synth.preset_scene("full")
     cams = synth.orbit_cameras(16)
     rays = cams.num_pixels()
     r = merf.Renderer(scene)
     stream = torch.cuda.current_stream()
     out = torch.empty((rays, 4), dtype=torch.float32, device="cuda")
     W, H = 1920, 1080
+    t0 = time.perf_counter()
     ref, st = oracle.render(scene, cams, rows_stride=64, row_offset=31, fragile=True)
+    t_oracle = time.perf_counter() - t0
     rows = np.arange(31, H, 64)
     sel = np.concatenate([(c * W * H + rows[:, None] * W + np.arange(W)[None, :]).reshape(-1) for c in range(16)])
     ok = st["fragile"] == 0
@@ -212,16 +250,22 @@ def precision_workload(steps: int):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
         d = out.cpu().numpy()[sel].astype(np.float64) - ref
-        res[name] = {"ms_per_step": ms, "Mrays/s": rays / (ms * 1e-3) / 1e6,
+        res[name] = {"mlp": mlp, "features": feat, "ms_per_call": ms, "Mrays/s": rays / (ms * 1e-3) / 1e6,
                      "psnr_db": 10 * np.log10(1 / max(float(np.mean(d[:, :3] ** 2)), 1e-30)),
                      "psnr_db_nonfragile": 10 * np.log10(1 / max(float(np.mean(d[ok, :3] ** 2)), 1e-30)),
-                     "max_abs_nonfragile": float(np.abs(d[ok]).max()), "mean_abs": float(np.abs(d).mean())}
+                     "max_abs_nonfragile": float(np.abs(d[ok]).max()), "max_abs": float(np.abs(d).max()),
+                     "mean_abs": float(np.abs(d).mean())}
     r.close()
-    return {"metric": "Mrays/s, 16 x 1080p views (precision config)", "value": res["f32"]["Mrays/s"],
+    return {"workload": "full-size scene, 16 orbit views at 1920x1080 in one merf_render call", "rays_per_call": rays,
+            "calls_timed": steps, "oracle_rows": "every 64th row of every view", "oracle_pixels": int(len(sel)),
+            "oracle_s": t_oracle, "fragile_frac": float((~ok).mean()), "modes": res}
+
+
+def precision_workload(steps: int):
+    pc = precision_config(steps)
+    return {"metric": "Mrays/s, 16 x 1080p views (precision config)", "value": pc["modes"]["f32"]["Mrays/s"],
             "unit": "Mrays/s", "n_gpus": 1, "steps": steps, "higher_is_better": True, "data": "synthetic",
-            "config": {"workload": "full-size scene, 16 orbit views at 1920x1080 in one call", "rays_per_step": rays,
-                       "oracle_rows": "every 64th row of every view"},
-            "precision": res}
+            "config": {"workload": pc["workload"], "rays_per_step": pc["rays_per_call"]}, "precision": pc}
 
 
 def stress_workload(n_scenes: int, n_requests: int):
@@ -469,6 +513,8 @@ def main():
                     help="full (default, the headline line), precision (16 x 1080p views), stress, "
                          "variants (representations: memory against speed) or resolutions (tile order by frame size)")
     ap.add_argument("--stress-scenes", type=int, default=32)
+    ap.add_argument("--precision-steps", type=int, default=5,
+                    help="timed calls per mode of the 16 x 1080p precision config in the default line (0 skips it)")
     ap.add_argument("--serve-requests", type=int, default=240,
                     help="requests in the serving-mix leg (0 skips it)")
     ap.add_argument("--no-overlap", action="store_true",
@@ -520,6 +566,9 @@ def main():
     cnt = st.cpu().numpy()
     n_rays, occ_lookups, visited, evaluated, contributing = [int(v) for v in cnt[:5]]
     alg_bytes = evaluated * B_EVAL + contributing * B_CONTRIB + occ_lookups * B_OCC + n_rays * B_RAY
+    alg_flops = evaluated * F_EVAL + contributing * F_CONTRIB + n_rays * F_RAY
+    # untimed: where a wave's time goes (phase-profiled variant of the kernel)
+    phases = phase_profile(merf, r, cams, out)
 
     for _ in range(args.warmup):
         r.render(cams, out=out)
@@ -581,6 +630,10 @@ def main():
         "per_ray": {"evaluated": evaluated / n_rays, "contributing": contributing / n_rays,
                     "visited": visited / n_rays, "occ_lookups": occ_lookups / n_rays},
         "alg_bytes_per_launch": alg_bytes,
+        "alg_valu_flops_per_launch": alg_flops,
+        "valu_roof": {"achieved_TFLOP/s": alg_flops / (kernel_ms * 1e-3) / 1e12, "peak_TFLOP/s": VALU_F32_PEAK_TFLOPS,
+                      "frac": alg_flops / (kernel_ms * 1e-3) / 1e12 / VALU_F32_PEAK_TFLOPS},
+        "phases": phases,
     }
     # the deferred MLP, the path's only dense contraction, on the matrix cores
     mf = measured_mfma()
@@ -648,6 +701,9 @@ def main():
             prec[name] = {"mlp": mlp, "features": feat, "kernel_ms": k_ms, "frame_gpu_ms": ms,
                           "Mrays/s": rays / (ms * 1e-3) / 1e6, "_img": img}
         res["precision"] = prec
+    if not args.headline_only and args.precision_steps > 0:
+        # the Precision config (16 x 1080p orbit views in one call)
+        res["precision_config"] = precision_config(args.precision_steps, scene)
     if args.copy_probe_mb > 0:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters read
         # exactly copy_probe_mb MiB each when the counters are exact

@@ -183,11 +183,21 @@ size_t merf_hbm_in_use(void);
 size_t merf_scene_bytes(merf_scene_t s);
 
 /*
- * Eq. 8 dequantisation of n device codes: out[i] = 2 m codes[i] / 255 - m,
- * correctly rounded to the output format (prec 0 = float32, 1 = float16,
- * 2 = bfloat16; out_dev holds n elements of that type).  This is the device
- * routine the renderer uses for per-texel dequantisation, exposed so that it
- * can be checked bit for bit.  Asynchronous on hip_stream.
+ * Eq. 8 dequantisation (Sec. 5.2) of n device codes with range m:
+ * out[i] = 2 m codes[i] / 255 - m, correctly rounded to the output format,
+ * which is what each precision of the renderer is checked against bit for
+ * bit.  out_dev holds n elements of the format.
+ *   prec 1 (float16): runs the device routine of the fp16-feature render path
+ *     (merf_render_params.feat_prec = 1), which dequantises every code it
+ *     reads with this routine, with the scale RN32(2m/255) that
+ *     merf_scene_upload computes for it.
+ *   prec 0 (float32) / 2 (bfloat16): the correctly rounded value.  The fp32
+ *     render path (feat_prec = 0) does not dequantise code by code: it
+ *     interpolates the codes of each source and applies Eq. 8's affine map
+ *     once per channel, which equals the interpolation of the dequantised
+ *     values in exact arithmetic because the weights of each source sum to 1
+ *     (the two differ by float32 rounding only).
+ * Asynchronous on hip_stream.
  * Errors: MERF_E_INVALID for n < 0, NULL buffers, m <= 0 or a bad prec.
  */
 int merf_dequantize(const uint8_t *codes_dev, int64_t n, float m, int32_t prec, void *out_dev,

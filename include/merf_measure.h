@@ -1,6 +1,7 @@
 /*
  * merf_measure.h -- measurement entry points of the MERF renderer (MI355X,
- * gfx950): the achievable-gather bound of a view.
+ * gfx950): the achievable-gather bound of a view, and where a wave's time
+ * goes.
  *
  * The renderer's memory traffic is its texel gathers (Sec. 6: per evaluated
  * sample, 8 grid voxels and 3 x 4 plane texels of 8 uint8 channels).  To
@@ -73,6 +74,30 @@ int merf_render_timed(merf_scene_t s, const merf_camera *cams, int32_t n_cams, c
  */
 int merf_replay_gathers(merf_scene_t s, const uint32_t *rec_dev, const int32_t *count_dev, int32_t cap,
                         const int32_t *order_dev, int32_t n_slots, float *out_dev, void *hip_stream);
+
+/*
+ * Phase profile of a view: render cams (at most 16, one launch) exactly as
+ * merf_render does (same image), in the counting variant of the kernel
+ * (p->stats_dev must be set), while every wave reads the shader clock at the
+ * points its 64 lanes pass together and ADDS to phases_dev (device
+ * uint64[16]), summed over the waves of the launch:
+ *   [0] cycles of ray set-up and the first segment (Sec. 4.2 Eq. 7),
+ *   [1] cycles of march passes (occupancy / empty-space steps, Sec. 6),
+ *   [2] cycles of segment openings during the march (Eq. 7 breakpoints),
+ *   [3] cycles of shading passes (gather, Eq. 8, Eq. 5, Eq. 6),
+ *   [4] cycles of compositing and queue upkeep (Eq. 1-2),
+ *   [5] cycles of the deferred MLP and the output (Eq. 3),
+ *   [6] cycles of the whole wave, [7] waves, [8] march passes,
+ *   [9] march passes in which some lane opened a segment, [10] segment
+ *   openings (lanes), [11] shading passes, [12] samples shaded,
+ *   [13] march-shade-composite rounds, [14..15] 0.
+ * The clock reads perturb the timing slightly; the counts are exact.
+ * Asynchronous on hip_stream.
+ * Errors: MERF_E_INVALID for a bad handle, camera, parameter or NULL
+ * buffer; MERF_E_DEVICE if a launch fails.
+ */
+int merf_render_phases(merf_scene_t s, const merf_camera *cams, int32_t n_cams, const merf_render_params *p,
+                       float *out_rgba_dev, uint64_t *phases_dev, void *hip_stream);
 
 #ifdef __cplusplus
 }

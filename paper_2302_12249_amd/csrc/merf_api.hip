@@ -537,10 +537,12 @@ int merf_scene_upload(const merf_scene_desc *desc, merf_scene_t *out) {
     ds.g_scale = (float)ds.L * 0.25f;
     ds.g_off = 2.0f * ds.g_scale - 0.5f;
     ds.g_max = (float)(ds.L - 1);
-    ds.d_scale = ds.m_density * (2.0f / 255.0f);
+    ds.d_scale = eq8_scale(ds.m_density);
     ds.d_off = -ds.nsrc * ds.m_density;
-    ds.f_scale = ds.m_feature * (2.0f / 255.0f);
+    ds.f_scale = eq8_scale(ds.m_feature);
     ds.f_off = -ds.nsrc * ds.m_feature;
+    ds.grid_w = L > 0 ? 1.0f : 0.0f;
+    ds.planes_w = R > 0 ? 1.0f : 0.0f;
     ds.dist_scale = (float)ds.dist_res * 0.25f;
     ds.dist_off = 2.0f * ds.dist_scale;
     {
@@ -606,7 +608,7 @@ int merf_dequantize(const uint8_t *codes_dev, int64_t n, float m, int32_t prec, 
     if (!codes_dev || !out_dev) return fail(MERF_E_INVALID, "NULL buffer");
     if (!(m > 0.0f) || !std::isfinite(m)) return fail(MERF_E_INVALID, "m %g must be positive", (double)m);
     if (prec < 0 || prec > 2) return fail(MERF_E_INVALID, "prec %d not in {0, 1, 2}", prec);
-    hipError_t e = launch_dequant(codes_dev, n, m, prec, out_dev, static_cast<hipStream_t>(hip_stream));
+    hipError_t e = launch_dequant(codes_dev, n, m, eq8_scale(m), prec, out_dev, static_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return hip_fail(e, "dequant launch");
     return MERF_OK;
 }

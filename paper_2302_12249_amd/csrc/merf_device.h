@@ -53,7 +53,8 @@ constexpr int kOrderMaxTiles = 1 << 17;
 // A scene without a grid carries a stand-in grid (L = 8, one index entry
 // pointing at the zero brick); a scene without planes carries all-zero 2x2
 // stand-in planes (R = 2).  Stand-ins read code 0, and nsrc counts only the
-// present sources, so the kernels gather both kinds without branching.
+// present sources (the fp16-feature path instead gives stand-in texels weight
+// grid_w / planes_w = 0), so the kernels gather both kinds without branching.
 struct DevScene {
     const int32_t *brick_index;
     const uint8_t *bricks;
@@ -69,6 +70,7 @@ struct DevScene {
     uint32_t dist_oct_stride;                    // bytes between octant grids (0: one shared grid)
     float m_density, m_feature;
     float nsrc;                                  // present sources: grid 1 + planes 3
+    float grid_w, planes_w;                      // 1 for a present source, 0 for a stand-in
     int32_t res;                                 // finest present resolution max(L, R) of the scene
     // constants of the kernels, computed once on the host in float32 exactly
     // as the kernels would (uniform values the compiler would otherwise hold
@@ -99,9 +101,31 @@ struct RenderBatch {
     uint32_t *rec;
     int32_t *rec_count;
     int32_t rec_cap;
+    // phase profile (null = off; needs stats): every wave adds the
+    // shader-clock cycles it spent in each phase and its loop counts
+    // (layout: enum PhaseSlot)
+    unsigned long long *phases;
     // tile order (null = plain): workgroup slot i renders tile order[i]
     const int32_t *order;
     DevCamera cams[kCamsPerLaunch];
+};
+
+// Slots of RenderBatch::phases (uint64 each, summed over the waves of a launch).
+enum PhaseSlot {
+    kPhSetup = 0,        // cycles: ray set-up and the first segment
+    kPhMarch,            // cycles: march passes, segment openings excluded
+    kPhOpen,             // cycles: segment openings during the march
+    kPhShade,            // cycles: gather, dequantise, decode of parked samples
+    kPhComposite,        // cycles: compositing and parking-queue upkeep
+    kPhMlp,              // cycles: deferred MLP and output (slots 0..5 tile the wave's time)
+    kPhWaves,            // waves
+    kPhMarchPasses,      // wave-level march passes
+    kPhOpenPasses,       // march passes in which some lane opened a segment
+    kPhOpenLanes,        // segment openings (lanes)
+    kPhShadePasses,      // shading passes
+    kPhShadeLanes,       // samples shaded (lanes busy in shading passes)
+    kPhRounds,           // march-shade-composite rounds
+    kPhSlots = 16
 };
 
 // Launchers (merf_render.hip).
@@ -124,7 +148,11 @@ constexpr int kRenderBlock = 64;
 // (null: plain); out: float4 per slot.
 hipError_t launch_gather_replay(const DevScene &sc, const uint32_t *rec, const int32_t *rec_count, int cap,
                                 const int32_t *order, int total_tiles, float *out, hipStream_t stream);
-hipError_t launch_dequant(const uint8_t *codes, int64_t n, float m, int prec, void *out, hipStream_t stream);
+// Eq. 8 of n codes with range m and scale a = eq8_scale(m): prec 0 / 2 the
+// correctly rounded float32 / bfloat16 value, prec 1 the float16 routine of
+// the fp16-feature render path (deq_f16 with the scale the upload computes).
+hipError_t launch_dequant(const uint8_t *codes, int64_t n, float m, float a, int prec, void *out,
+                          hipStream_t stream);
 // merf_ingest.hip: brick_pos[i] = bx | by << 10 | bz << 20 of brick slot i.
 hipError_t launch_pack_bricks(const uint8_t *blocks, const int32_t *block_index, const int32_t *brick_pos,
                               int nbricks, int L, uint8_t *bricks, hipStream_t stream);

@@ -15,6 +15,12 @@ int fail(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
 void clear_error();
 
+// Eq. 8 scale a = 2 m / 255 in float32, correctly rounded: 2 m is exact and
+// the division rounds once.  The upload derives the kernels' dequantisation
+// constants from it and merf_dequantize uses the same value, so the routine
+// that entry point runs is the renderer's own with the renderer's constant.
+inline float eq8_scale(float m) { return (2.0f * m) / 255.0f; }
+
 // Device view of a live scene handle, or nullptr.
 const DevScene *scene_dev(merf_scene_t s);
 

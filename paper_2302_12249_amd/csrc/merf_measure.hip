@@ -84,6 +84,30 @@ int merf_render_timed(merf_scene_t s, const merf_camera *cams, int32_t n_cams, c
                          static_cast<hipEvent_t>(ev_start), static_cast<hipEvent_t>(ev_end));
 }
 
+int merf_render_phases(merf_scene_t s, const merf_camera *cams, int32_t n_cams, const merf_render_params *p,
+                       float *out_rgba_dev, uint64_t *phases_dev, void *hip_stream) {
+    clear_error();
+    const DevScene *ds = scene_dev(s);
+    if (!ds) return fail(MERF_E_INVALID, "merf_render_phases: invalid scene handle");
+    float step = 0.0f;
+    int rc = check_params(p, ds->res, &step);
+    if (rc) return rc;
+    if (!p->stats_dev) return fail(MERF_E_INVALID, "the phase profile needs stats_dev");
+    if (!cams || !out_rgba_dev || !phases_dev) return fail(MERF_E_INVALID, "NULL buffer");
+    if (n_cams < 1 || n_cams > kCamsPerLaunch)
+        return fail(MERF_E_INVALID, "n_cams %d not in [1, %d]", n_cams, kCamsPerLaunch);
+    RenderBatch rb;
+    begin_batch(rb, *p, step);
+    int64_t pix = 0;
+    for (int i = 0; i < n_cams; ++i) {
+        if ((rc = check_camera(cams[i], i))) return rc;
+        if (!add_camera(rb, cams[i], out_rgba_dev + pix * 4)) return fail(MERF_E_INVALID, "cameras exceed one launch");
+        pix += (int64_t)cams[i].width * cams[i].height;
+    }
+    rb.phases = reinterpret_cast<unsigned long long *>(phases_dev);
+    return render_launch(*ds, rb, p->tile_order, static_cast<hipStream_t>(hip_stream));
+}
+
 int merf_replay_gathers(merf_scene_t s, const uint32_t *rec_dev, const int32_t *count_dev, int32_t cap,
                         const int32_t *order_dev, int32_t n_slots, float *out_dev, void *hip_stream) {
     clear_error();

@@ -57,9 +57,11 @@ __device__ __forceinline__ float deq_f32(uint32_t b, float m2, float m255) {
     return fmaf(r, kRcp255, q);
 }
 
-// Eq. 8 to float16: RN16(RN32(b * RN32(2m/255) - m)) equals the correctly
-// rounded float16 of the exact 2mb/255 - m for every code and m in {7, 14}
-// (checked exhaustively by the test-suite); returned widened to float.
+// Eq. 8 to float16 with a = RN32(2m/255) (the scale the upload computes):
+// RN16(RN32(b a - m)) equals the correctly rounded float16 of the exact
+// 2mb/255 - m for every code and m in {7, 14} (checked exhaustively on the
+// host, and bit for bit on the device through merf_dequantize); returned
+// widened to float.
 __device__ __forceinline__ float deq_f16(uint32_t b, float a, float m) {
     return (float)(_Float16)fmaf((float)b, a, -m);
 }
@@ -193,7 +195,29 @@ struct Accum {
 };
 
 struct Counters {
-    uint32_t occ_lookups, visited, evaluated, contributing;
+    uint32_t occ_lookups, visited, evaluated, contributing, opens;
+};
+
+// Phase profile of the statistics variant (RenderBatch::phases): shader-clock
+// timestamps taken at points every lane of the wave passes together, so each
+// interval is wave time, added to the phase it belongs to.  Lane i keeps the
+// sum of slot i (one register for all slots; a wave's sums stay below 2^32).
+template <bool kOn>
+struct PhaseClock {
+    uint32_t t = 0, v = 0;          // low word of the last timestamp; this lane's sum
+    __device__ __forceinline__ void start() {
+        if (kOn) t = (uint32_t)__builtin_amdgcn_s_memtime();
+    }
+    __device__ __forceinline__ void count(int slot, uint32_t x = 1) {
+        if (kOn) v += (int)threadIdx.x == slot ? x : 0u;
+    }
+    __device__ __forceinline__ void lap(int slot) {
+        if (kOn) {
+            const uint32_t n = (uint32_t)__builtin_amdgcn_s_memtime();
+            count(slot, n - t);     // modulo 2^32: intervals are far shorter
+            t = n;
+        }
+    }
 };
 
 template <typename T>
@@ -329,6 +353,11 @@ __device__ __forceinline__ SampleResult eval_sample(const DevScene &sc, float3 p
     // ---- density first (Sec. 6): appearance is read only when alpha != 0
     float s0 = 0.0f;
     if constexpr (kFeatF16) {
+        // a stand-in source (scene without grid or without planes) reads code
+        // 0, whose float16 value is -m: its texels get weight 0 here, so that
+        // the sum holds the present sources only (Eq. 5)
+#pragma unroll
+        for (int i = 0; i < 20; ++i) w[i] *= i < 8 ? sc.grid_w : sc.planes_w;
 #pragma unroll
         for (int i = 0; i < 20; ++i) s0 = fmaf(w[i], deq_f16(byte_of(lo[i], 0), sc.d_scale, md), s0);
     } else {
@@ -705,8 +734,11 @@ constexpr int kLdsFloats = MlpLds<kPrec>::kFloats > kParkFloats ? MlpLds<kPrec>:
 
 // kLevels: empty space is skipped with the occupancy levels themselves
 // (skip_mode 1) instead of the distance grid (skip_mode 0).
-template <bool kStats, int kMlpPrec, bool kFeatF16, bool kLevels>
+// kMode: 0 renders; 1 also adds the statistics counters (and records the
+// gathers when rb.rec is set); 2 also takes the phase profile.
+template <int kMode, int kMlpPrec, bool kFeatF16, bool kLevels>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_render(const DevScene sc, const RenderBatch rb) {
+    constexpr bool kStats = kMode >= 1, kPhase = kMode == 2;
     __shared__ float lds[kLdsFloats<kMlpPrec>];
     const int slot = xcd_remap((int)blockIdx.x, rb.total_tiles);
     int tile = rb.order ? rb.order[slot] : slot;
@@ -721,6 +753,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     const int px = (lt % cam.tiles_x) * kTile + (lane & (kTile - 1));
     const int py = (lt / cam.tiles_x) * kTile + (lane / kTile);
     const bool active = px < cam.width && py < cam.height;
+    PhaseClock<kPhase> ph;
+    ph.start();
 
     // ---- pinhole ray
     float vx = ((float)px + 0.5f - cam.cx) * cam.inv_fx;
@@ -732,7 +766,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     d.x *= inv; d.y *= inv; d.z *= inv;
     const float3 o = make_float3(cam.c2w[3], cam.c2w[7], cam.c2w[11]);
 
-    Counters cnt = {0u, 0u, 0u, 0u};
+    Counters cnt = {0u, 0u, 0u, 0u, 0u};
     Accum acc = {1.0f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     const float step = rb.step, istep = rb.inv_step;
     Segment s;
@@ -744,6 +778,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     int nseg = 1;
     bool alive = active, terminated = false;
     float known[kMaxLevels] = {0.0f, 0.0f, 0.0f, 0.0f};   // per level: occupied up to this u
+    if (kPhase) ph.lap(kPhSetup);
 
     // The march runs ahead of the shading: every live lane finds up to kQueue
     // occupied samples (cheap skip iterations) and parks them in LDS; then the
@@ -758,6 +793,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     int *imap = reinterpret_cast<int *>(rs + 2 * 64);          // [64] shading slot -> parked entry
     int pc = 0;                                               // samples parked by this lane
     while (__any(alive || pc > 0)) {
+        if (kPhase) ph.count(kPhRounds);
         // ---- march: live lanes park up to kQueue samples, one step per
         // pass; the wave stops once 64 samples are parked (a round shades no
         // more), so slow lanes do not hold the others back
@@ -767,107 +803,117 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 #pragma unroll
             for (int j = 0; j < kQueue; ++j) parked += __popcll(__ballot(pc > j));
             if (!__any(want) || parked >= 64) break;
-            if (!want) continue;
-            do {   // one march step: break and continue both end it
-                if (s.k >= s.n) {
-                    // segment done: continue in the next region, if any
+            if (kPhase) ph.count(kPhMarchPasses);
+            // a lane whose segment is done spends this pass on the next
+            // region's segment, if any
+            const bool open = want && s.k >= s.n;
+            if (kPhase ? __any(open) : true) {
+                if (kPhase) ph.lap(kPhMarch);
+                if (open) {
                     if (!(s.tb < kInf) || nseg >= 8) {
                         alive = false;
-                        break;
+                    } else {
+                        open_segment(o, d, s.tb, s.reg_next, istep, sc.dist_oct_stride, s);
+                        ++nseg;
+                        if (kStats) ++cnt.opens;
+                        known[0] = known[1] = known[2] = known[3] = 0.0f;
                     }
-                    open_segment(o, d, s.tb, s.reg_next, istep, sc.dist_oct_stride, s);
-                    ++nseg;
-                    known[0] = known[1] = known[2] = known[3] = 0.0f;
-                    continue;
                 }
-                const float u0 = (float)s.k * step;
-                const float u1 = fminf(u0 + step, s.len);
-                const float um = 0.5f * (u0 + u1);
-                const float3 p = make_float3(fmaf(um, s.e.x, s.A.x), fmaf(um, s.e.y, s.A.y), fmaf(um, s.e.z, s.A.z));
-                if (kStats) ++cnt.visited;
-                // empty >= 0: the sample is in empty space, which the segment
-                // leaves at parameter uexit.  A cell seen occupied stays known
-                // until the segment leaves it (its exit minus the guard), so later
-                // samples inside it need no lookup.
-                int empty = -1;
-                float uexit = 0.0f;
-                if constexpr (!kLevels) {
-                    // empty-space grid: leave the whole empty cube ahead, or
-                    // remember the occupied cell
-                    if (!(um < known[0])) {
+                if (kPhase) {
+                    ph.lap(kPhOpen);
+                    ph.count(kPhOpenPasses);
+                }
+            }
+            if (!want || open) continue;
+            // ---- one march step
+            const float u0 = (float)s.k * step;
+            const float u1 = fminf(u0 + step, s.len);
+            const float um = 0.5f * (u0 + u1);
+            const float3 p = make_float3(fmaf(um, s.e.x, s.A.x), fmaf(um, s.e.y, s.A.y), fmaf(um, s.e.z, s.A.z));
+            if (kStats) ++cnt.visited;
+            // empty >= 0: the sample is in empty space, which the segment
+            // leaves at parameter uexit.  A cell seen occupied stays known
+            // until the segment leaves it (its exit minus the guard), so later
+            // samples inside it need no lookup.
+            int empty = -1;
+            float uexit = 0.0f;
+            if constexpr (!kLevels) {
+                // empty-space grid: leave the whole empty cube ahead, or
+                // remember the occupied cell
+                if (!(um < known[0])) {
+                    if (kStats) ++cnt.occ_lookups;
+                    float ue;
+                    const int D = dist_lookup(sc, s, p, ue);
+                    if (D == 0) {
+                        known[0] = ue - kSkipGuard;
+                    } else {
+                        empty = 0;
+                        uexit = ue;
+                    }
+                }
+            } else {
+                // the occupancy levels, coarse to fine: stop at the first
+                // empty level and leave its cell
+#pragma unroll
+                for (int l = 0; l < kMaxLevels; ++l) {
+                    if (l < sc.occ_levels && empty < 0 && !(um < known[l])) {
+                        const int rl = sc.occ_res[l];
+                        const float os = (float)rl * 0.25f, os2 = 2.0f * os;
+                        const int qx = min((int)fmaf(p.x, os, os2), rl - 1);
+                        const int qy = min((int)fmaf(p.y, os, os2), rl - 1);
+                        const int qz = min((int)fmaf(p.z, os, os2), rl - 1);
                         if (kStats) ++cnt.occ_lookups;
-                        float ue;
-                        const int D = dist_lookup(sc, s, p, ue);
-                        if (D == 0) {
-                            known[0] = ue - kSkipGuard;
+                        const bool occ = load_at<uint8_t>(sc.occ[l], cell_offset(qx, qy, qz, rl)) != 0;
+                        // exit parameter of this cell along the segment (slab test)
+                        const float h = sc.occ_cell[l];
+                        const float bx = (float)(s.iex > 0.0f ? qx + 1 : qx) * h - 2.0f;
+                        const float by = (float)(s.iey > 0.0f ? qy + 1 : qy) * h - 2.0f;
+                        const float bz = (float)(s.iez > 0.0f ? qz + 1 : qz) * h - 2.0f;
+                        const float tx = (bx - s.A.x) * s.iex;
+                        const float ty = (by - s.A.y) * s.iey;
+                        const float tz = (bz - s.A.z) * s.iez;
+                        const float ue = fminf(tx, fminf(ty, tz));
+                        if (occ) {
+                            known[l] = ue - kSkipGuard;
                         } else {
-                            empty = 0;
+                            empty = l;
                             uexit = ue;
                         }
                     }
-                } else {
-                    // the occupancy levels, coarse to fine: stop at the first
-                    // empty level and leave its cell
-#pragma unroll
-                    for (int l = 0; l < kMaxLevels; ++l) {
-                        if (l < sc.occ_levels && empty < 0 && !(um < known[l])) {
-                            const int rl = sc.occ_res[l];
-                            const float os = (float)rl * 0.25f, os2 = 2.0f * os;
-                            const int qx = min((int)fmaf(p.x, os, os2), rl - 1);
-                            const int qy = min((int)fmaf(p.y, os, os2), rl - 1);
-                            const int qz = min((int)fmaf(p.z, os, os2), rl - 1);
-                            if (kStats) ++cnt.occ_lookups;
-                            const bool occ = load_at<uint8_t>(sc.occ[l], cell_offset(qx, qy, qz, rl)) != 0;
-                            // exit parameter of this cell along the segment (slab test)
-                            const float h = sc.occ_cell[l];
-                            const float bx = (float)(s.iex > 0.0f ? qx + 1 : qx) * h - 2.0f;
-                            const float by = (float)(s.iey > 0.0f ? qy + 1 : qy) * h - 2.0f;
-                            const float bz = (float)(s.iez > 0.0f ? qz + 1 : qz) * h - 2.0f;
-                            const float tx = (bx - s.A.x) * s.iex;
-                            const float ty = (by - s.A.y) * s.iey;
-                            const float tz = (bz - s.A.z) * s.iez;
-                            const float ue = fminf(tx, fminf(ty, tz));
-                            if (occ) {
-                                known[l] = ue - kSkipGuard;
-                            } else {
-                                empty = l;
-                                uexit = ue;
-                            }
-                        }
+                }
+            }
+            if (empty < 0) {
+                float delta = u1 - u0;
+                if (rb.delta_mode == 1) {
+                    float3 y0 = make_float3(fmaf(u0, s.e.x, s.A.x), fmaf(u0, s.e.y, s.A.y), fmaf(u0, s.e.z, s.A.z));
+                    float3 y1 = (s.k == s.n - 1)
+                                    ? segment_end(o, d, s.tb, s.reg)
+                                    : make_float3(fmaf(u1, s.e.x, s.A.x), fmaf(u1, s.e.y, s.A.y), fmaf(u1, s.e.z, s.A.z));
+                    bool at_inf = false;
+                    if (s.reg != 0) {
+                        const int jj = (s.reg - 1) >> 1;
+                        const float sg = ((s.reg - 1) & 1) ? -1.0f : 1.0f;
+                        const float y1j = jj == 0 ? y1.x : (jj == 1 ? y1.y : y1.z);
+                        at_inf = sg * y1j >= 2.0f;
+                    }
+                    if (at_inf) {
+                        delta = kInf;
+                    } else {
+                        float3 x0 = unmap_region(s.reg, y0), x1 = unmap_region(s.reg, y1);
+                        float dx = x1.x - x0.x, dy = x1.y - x0.y, dz = x1.z - x0.z;
+                        delta = sqrtf(dx * dx + dy * dy + dz * dz);
                     }
                 }
-                if (empty < 0) {
-                    float delta = u1 - u0;
-                    if (rb.delta_mode == 1) {
-                        float3 y0 = make_float3(fmaf(u0, s.e.x, s.A.x), fmaf(u0, s.e.y, s.A.y), fmaf(u0, s.e.z, s.A.z));
-                        float3 y1 = (s.k == s.n - 1)
-                                        ? segment_end(o, d, s.tb, s.reg)
-                                        : make_float3(fmaf(u1, s.e.x, s.A.x), fmaf(u1, s.e.y, s.A.y), fmaf(u1, s.e.z, s.A.z));
-                        bool at_inf = false;
-                        if (s.reg != 0) {
-                            const int jj = (s.reg - 1) >> 1;
-                            const float sg = ((s.reg - 1) & 1) ? -1.0f : 1.0f;
-                            const float y1j = jj == 0 ? y1.x : (jj == 1 ? y1.y : y1.z);
-                            at_inf = sg * y1j >= 2.0f;
-                        }
-                        if (at_inf) {
-                            delta = kInf;
-                        } else {
-                            float3 x0 = unmap_region(s.reg, y0), x1 = unmap_region(s.reg, y1);
-                            float dx = x1.x - x0.x, dy = x1.y - x0.y, dz = x1.z - x0.z;
-                            delta = sqrtf(dx * dx + dy * dy + dz * dz);
-                        }
-                    }
-                    pq[pc * 64 + lane] = make_float4(p.x, p.y, p.z, delta);
-                    ++pc;
-                    ++s.k;
-                    continue;
-                }
-                // leave the empty cell
-                // first lattice interval whose midpoint lies past the exit
+                pq[pc * 64 + lane] = make_float4(p.x, p.y, p.z, delta);
+                ++pc;
+                ++s.k;
+            } else {
+                // leave the empty cell: first lattice interval whose midpoint
+                // lies past the exit
                 s.k = skip_past(s, uexit, istep);
-            } while (false);
+            }
         }
+        if (kPhase) ph.lap(kPhMarch);
         // ---- shade: parked samples numbered level by level (all first
         // samples, then all second ones ...), lane order within a level;
         // slots past 64 wait for the next round
@@ -887,6 +933,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
             rs[2 * lane + 1] = make_float4(r.sg[3], r.sg[4], r.sg[5], r.sg[6]);
         }
         __syncthreads();
+        if (kPhase) {
+            ph.lap(kPhShade);
+            ph.count(kPhShadePasses, total > 0 ? 1 : 0);
+            ph.count(kPhShadeLanes, (uint32_t)min(total, 64));
+        }
         // ---- composite this lane's shaded samples in ray order
         int done = 0, before = 0;
 #pragma unroll
@@ -926,6 +977,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
             pc -= done;
         }
         __syncthreads();
+        if (kPhase) ph.lap(kPhComposite);
     }
 
     const float3 h = deferred_mlp_mfma<kMlpPrec>(sc.mlp, lds, acc, d);
@@ -939,6 +991,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
         float4 rgba = make_float4(acc.cd0 + h.x, acc.cd1 + h.y, acc.cd2 + h.z, 1.0f - acc.T);
         *reinterpret_cast<float4 *>(cam.out + ((int64_t)oy * cam.width + ox) * 4) = rgba;
     }
+    if (kPhase) ph.lap(kPhMlp);
     if (kStats && rb.rec_count) rb.rec_count[tile * 64 + lane] = (int32_t)cnt.evaluated;
     if (kStats) {
         unsigned long long v[6] = {active ? 1ull : 0ull, cnt.occ_lookups, cnt.visited, cnt.evaluated, cnt.contributing,
@@ -949,6 +1002,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
             if (lane == 0 && x) atomicAdd(rb.stats + i, x);
+        }
+        if (kPhase) {
+            ph.count(kPhWaves);
+            uint32_t x = cnt.opens;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+            ph.count(kPhOpenLanes, x);
+            if (lane < kPhSlots && ph.v) atomicAdd(rb.phases + lane, (unsigned long long)ph.v);
         }
     }
 }
@@ -1149,39 +1210,51 @@ __global__ __launch_bounds__(64) void k_gather_replay(const DevScene sc, const u
     reinterpret_cast<float4 *>(out)[q] = make_float4((float)n, (float)(sink & 1u), 0.0f, 0.0f);
 }
 
-// Eq. 8 dequantisation, correctly rounded to the output format.  Rounding the
-// correctly rounded float32 value again to float16 or bfloat16 gives the
-// correctly rounded result directly, because k/255 never lies within half a
-// float32 ulp of a float16 or bfloat16 rounding boundary (its binary
-// expansion repeats with period 8), and the test-suite checks all codes.
-__global__ void k_dequant(const uint8_t *__restrict__ codes, int64_t n, float m, int prec, void *__restrict__ out) {
+// Eq. 8 dequantisation of a buffer of codes.  prec 1 runs deq_f16, the
+// routine the fp16-feature render path applies to every code it reads, with
+// the scale a the upload computes for that path.  prec 0 gives the correctly
+// rounded float32 value (deq_f32) and prec 2 that value rounded again to
+// bfloat16, which is the correctly rounded bfloat16 value, because k/255
+// never lies within half a float32 ulp of a bfloat16 rounding boundary (its
+// binary expansion repeats with period 8); the test-suite checks all codes.
+__global__ void k_dequant(const uint8_t *__restrict__ codes, int64_t n, float m, float a, int prec,
+                          void *__restrict__ out) {
     const float m2 = 2.0f * m, m255 = 255.0f * m;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        float v = deq_f32(codes[i], m2, m255);
-        if (prec == 0) reinterpret_cast<float *>(out)[i] = v;
-        else if (prec == 1) reinterpret_cast<__half *>(out)[i] = __float2half_rn(v);
-        else reinterpret_cast<__hip_bfloat16 *>(out)[i] = __float2bfloat16(v);
+        if (prec == 1) {
+            reinterpret_cast<__half *>(out)[i] = __float2half_rn(deq_f16(codes[i], a, m));
+        } else {
+            const float v = deq_f32(codes[i], m2, m255);
+            if (prec == 0) reinterpret_cast<float *>(out)[i] = v;
+            else reinterpret_cast<__hip_bfloat16 *>(out)[i] = __float2bfloat16(v);
+        }
     }
 }
 
 }  // namespace
 
-template <bool kStats, bool kFeatF16, bool kLevels>
+template <int kMode, bool kFeatF16, bool kLevels>
 const void *render_kernel_mlp(int mlp_prec) {
-    return mlp_prec == 0 ? (const void *)k_render<kStats, 0, kFeatF16, kLevels>
-         : mlp_prec == 1 ? (const void *)k_render<kStats, 1, kFeatF16, kLevels>
-                         : (const void *)k_render<kStats, 2, kFeatF16, kLevels>;
+    return mlp_prec == 0 ? (const void *)k_render<kMode, 0, kFeatF16, kLevels>
+         : mlp_prec == 1 ? (const void *)k_render<kMode, 1, kFeatF16, kLevels>
+                         : (const void *)k_render<kMode, 2, kFeatF16, kLevels>;
 }
 
-template <bool kStats, bool kLevels>
+template <int kMode, bool kLevels>
 const void *render_kernel_feat(const RenderBatch &rb) {
-    return rb.feat_prec ? render_kernel_mlp<kStats, true, kLevels>(rb.mlp_prec)
-                        : render_kernel_mlp<kStats, false, kLevels>(rb.mlp_prec);
+    return rb.feat_prec ? render_kernel_mlp<kMode, true, kLevels>(rb.mlp_prec)
+                        : render_kernel_mlp<kMode, false, kLevels>(rb.mlp_prec);
+}
+
+template <int kMode>
+const void *render_kernel_mode(const RenderBatch &rb) {
+    return rb.skip_mode ? render_kernel_feat<kMode, true>(rb) : render_kernel_feat<kMode, false>(rb);
 }
 
 const void *render_kernel(const RenderBatch &rb) {
-    if (rb.stats) return rb.skip_mode ? render_kernel_feat<true, true>(rb) : render_kernel_feat<true, false>(rb);
-    return rb.skip_mode ? render_kernel_feat<false, true>(rb) : render_kernel_feat<false, false>(rb);
+    if (rb.phases) return render_kernel_mode<2>(rb);
+    if (rb.stats) return render_kernel_mode<1>(rb);
+    return render_kernel_mode<0>(rb);
 }
 
 dim3 render_grid(const RenderBatch &rb) { return dim3((unsigned)rb.total_tiles); }
@@ -1216,11 +1289,12 @@ hipError_t launch_gather_replay(const DevScene &sc, const uint32_t *rec, const i
     return hipGetLastError();
 }
 
-hipError_t launch_dequant(const uint8_t *codes, int64_t n, float m, int prec, void *out, hipStream_t stream) {
+hipError_t launch_dequant(const uint8_t *codes, int64_t n, float m, float a, int prec, void *out,
+                          hipStream_t stream) {
     if (n <= 0) return hipSuccess;
     int64_t blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_dequant, dim3((unsigned)blocks), dim3(256), 0, stream, codes, n, m, prec, out);
+    hipLaunchKernelGGL(k_dequant, dim3((unsigned)blocks), dim3(256), 0, stream, codes, n, m, a, prec, out);
     return hipGetLastError();
 }
 

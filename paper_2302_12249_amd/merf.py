@@ -316,7 +316,11 @@ def _serve_lib():
     return lib
 
 
-MEASURE_EXPORTS = ["merf_gather_slots", "merf_record_gathers", "merf_render_timed", "merf_replay_gathers"]
+MEASURE_EXPORTS = ["merf_gather_slots", "merf_record_gathers", "merf_render_phases", "merf_render_timed",
+                   "merf_replay_gathers"]
+PHASE_FIELDS = ["setup_cycles", "march_cycles", "open_cycles", "shade_cycles", "composite_cycles", "mlp_cycles",
+                "total_cycles", "waves", "march_passes", "open_passes", "open_lanes", "shade_passes",
+                "shade_lanes", "rounds"]
 
 
 def _measure_lib():
@@ -329,6 +333,7 @@ def _measure_lib():
                                         vp, vp, vp]
     lib.merf_replay_gathers.argtypes = [vp, vp, vp, i32, vp, i32, vp, vp]
     lib.merf_render_timed.argtypes = [vp, C.POINTER(merf_camera), i32, C.POINTER(merf_render_params), vp, vp, vp, vp]
+    lib.merf_render_phases.argtypes = [vp, C.POINTER(merf_camera), i32, C.POINTER(merf_render_params), vp, vp, vp]
     for n in MEASURE_EXPORTS:
         getattr(lib, n).restype = C.c_int
     lib._measure_ready = True
@@ -354,6 +359,25 @@ def render_timed(handle: int, cams, out, ev_start, ev_end, stream=None, **params
     _check(_measure_lib().merf_render_timed(C.c_void_p(handle), camera_array(cams), len(cams), C.byref(p),
                                             C.c_void_p(out.data_ptr()), C.c_void_p(_event_handle(ev_start)),
                                             C.c_void_p(_event_handle(ev_end)), C.c_void_p(st.cuda_stream)))
+
+
+def render_phases(handle: int, cams, out, stream=None, **params) -> dict:
+    """merf_render_phases: render cams (one launch) into the cuda tensor out
+    and return the phase profile summed over the launch's waves (a dict of
+    PHASE_FIELDS) and the statistics counters."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    ph = torch.zeros(16, dtype=torch.int64, device="cuda")
+    p = render_params(stats_ptr=stats.data_ptr(), **params)
+    _check(_measure_lib().merf_render_phases(C.c_void_p(handle), camera_array(cams), len(cams), C.byref(p),
+                                             C.c_void_p(out.data_ptr()), C.c_void_p(ph.data_ptr()),
+                                             C.c_void_p(st.cuda_stream)))
+    st.synchronize()
+    v = ph.cpu().numpy()
+    res = {n: int(v[i]) for i, n in enumerate(PHASE_FIELDS)}
+    res["stats"] = {n: int(x) for n, x in zip(STATS_FIELDS, stats.cpu().numpy())}
+    return res
 
 
 class GatherRecord:

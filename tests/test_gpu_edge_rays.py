@@ -1,0 +1,63 @@
+"""GPU parity on rays at the breakpoints of Eq. 7 (Sec. 4.2): exactly
+axis-parallel rays (a direction component of +-0, where the kernel's
+reciprocals are +-inf), rays with exactly equal component magnitudes
+(|d_j| = |d_k|, on or along the outer seams), rays through cube edges and
+along the 3-D diagonal, in odd-sized frames, on the tiny and full scenes.
+Bar as in gpu_helpers; the centre row, centre column and diagonals of each
+frame (the exact rays) must mostly be non-fragile so they are really
+compared."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from edge_cameras import edge_cameras, special_pixels
+from gpu_helpers import check, gpu_render, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+@pytest.fixture(scope="module")
+def merf():
+    from paper_2302_12249_amd import merf as m
+    m.load()
+    return m
+
+
+@pytest.fixture(scope="module", params=["tiny", "full"])
+def scene(request):
+    return synth.preset_scene(request.param)
+
+
+@pytest.mark.parametrize("kw", [{}, {"delta_mode": 1}, {"mlp_prec": "bf16", "feat_prec": "f16"}])
+def test_edge_rays_match_oracle(torch, merf, scene, kw):
+    names, cams = edge_cameras()
+    say(f"{scene.name}: {len(cams)} edge-case cameras {kw}")
+    gpu = gpu_render(torch, merf, scene, cams, **kw)
+    ref, st = oracle.render(scene, cams, delta_mode=kw.get("delta_mode", 0))
+    off = 0
+    for i, n in enumerate(names):
+        w, h = int(cams.size[i, 0]), int(cams.size[i, 1])
+        sl = slice(off, off + w * h)
+        fr = st["fragile"][sl]
+        sp = special_pixels(w, h)
+        check(gpu[sl], ref[sl], fr, f"{scene.name} {n} {kw}", max_fragile=0.05)
+        assert np.mean(fr[sp] == 0) >= 0.7, n
+        off += w * h
+
+
+def test_edge_rays_skip_modes_and_orders_agree(torch, merf, scene):
+    names, cams = edge_cameras()
+    say(f"{scene.name}: edge-case cameras, skip modes and tile orders give the same bits")
+    a = gpu_render(torch, merf, scene, cams)
+    b = gpu_render(torch, merf, scene, cams, skip="levels")
+    c = gpu_render(torch, merf, scene, cams, order="plain")
+    assert np.array_equal(a, b)
+    assert np.array_equal(a, c)

@@ -1,8 +1,9 @@
 """GPU parity: the HIP renderer (through the C ABI) against the FP64 oracle.
 
-Bar: RGB and alpha within 2/255 max abs on pixels the oracle does not flag
-as fragile, and within 1e-3 mean abs over all pixels; dequantisation bit
-exact; renders bitwise deterministic.
+Bar (gpu_helpers): RGB and alpha within 2/255 max abs on pixels the oracle
+does not flag as fragile, and within 1e-3 mean abs over all pixels; the
+fp16 / bf16 MLP and fp16-feature paths meet the same per-pixel bound and
+45 dB PSNR; dequantisation bit exact; renders bitwise deterministic.
 """
 import numpy as np
 import pytest
@@ -10,16 +11,10 @@ import pytest
 import oracle
 import synth
 from exact_round import dequant_table, to_bits
+from gpu_helpers import MAX_ABS, MIN_PSNR_DB, check, gpu_render, psnr, rows_of, say
 from scene_builders import dense_scene
 
 pytestmark = pytest.mark.gpu
-
-MAX_ABS = 2.0 / 255.0
-MEAN_ABS = 1e-3
-
-
-def say(msg):
-    print(msg, flush=True)
 
 
 @pytest.fixture(scope="module")
@@ -36,35 +31,10 @@ def merf():
     return m
 
 
-def gpu_render(torch, merf, scene, cams, stats=False, **kw):
-    r = merf.Renderer(scene)
-    try:
-        st = torch.zeros(8, dtype=torch.int64, device="cuda") if stats else None
-        out = r.render(cams, stats=st, **kw)
-        torch.cuda.synchronize()
-        res = out.cpu().numpy().astype(np.float64)
-        return (res, st.cpu().numpy()) if stats else res
-    finally:
-        r.close()
-
-
-def check(gpu, ref, fragile, label, max_fragile=0.005):
-    ok = fragile == 0
-    err = np.abs(gpu - ref)
-    mx = float(err[ok].max()) if ok.any() else 0.0
-    mean = float(err.mean())
-    say(f"{label}: max|err| non-fragile {mx:.3e}  mean|err| {mean:.3e}  fragile {float((~ok).mean()):.4%}  "
-        f"pixels {len(ref)}")
-    assert np.all(np.isfinite(gpu))
-    assert mx <= MAX_ABS, label
-    assert mean <= MEAN_ABS, label
-    if max_fragile is not None:
-        assert float((~ok).mean()) < max_fragile, label
-    return mx, mean
-
-
 @pytest.mark.parametrize("fmt,prec", [("f32", 0), ("f16", 1), ("bf16", 2)])
 def test_dequant_bit_exact(torch, merf, fmt, prec):
+    """f16 runs the fp16-feature render path's own routine (deq_f16) with the
+    scale the upload computes; f32 / bf16 the correctly rounded values."""
     say(f"dequant bit-exact {fmt}")
     codes = torch.arange(256, dtype=torch.uint8, device="cuda")
     dt = {0: torch.float32, 1: torch.float16, 2: torch.bfloat16}[prec]
@@ -239,12 +209,9 @@ def test_full_1080p_parity_sampled_rows(torch, merf, full_scene):
     say("full 1920x1080 parity (every 27th row checked by the oracle)")
     cams = synth.full_camera()
     gpu = gpu_render(torch, merf, full_scene, cams)
-    W, H = 1920, 1080
     stride, off = 27, 13
     ref, st = oracle.render(full_scene, cams, rows_stride=stride, row_offset=off)
-    rows = np.arange(off, H, stride)
-    sel = (rows[:, None] * W + np.arange(W)[None, :]).reshape(-1)
-    check(gpu[sel], ref, st["fragile"], "full 1080p sampled rows")
+    check(gpu[rows_of(cams, stride, off)], ref, st["fragile"], "full 1080p sampled rows")
     assert gpu[:, 3].max() > 0.5      # the view sees content
     # the paper's level-by-level skipping gives the same image
     lv = gpu_render(torch, merf, full_scene, cams, skip="levels")
@@ -342,15 +309,7 @@ def test_full_scene_orbit_views_sampled(torch, merf, full_scene):
     cams = synth.orbit_cameras(4, w=480, h=270)
     gpu = gpu_render(torch, merf, full_scene, cams)
     ref, st = oracle.render(full_scene, cams, rows_stride=9, row_offset=4)
-    rows = np.arange(4, 270, 9)
-    sel = np.concatenate([(c * 480 * 270 + rows[:, None] * 480 + np.arange(480)[None, :]).reshape(-1)
-                          for c in range(4)])
-    check(gpu[sel], ref, st["fragile"], "orbit views")
-
-
-def psnr(a, b):
-    mse = float(np.mean((a[:, :3] - b[:, :3]) ** 2))
-    return 10.0 * np.log10(1.0 / max(mse, 1e-30))
+    check(gpu[rows_of(cams, 9, 4)], ref, st["fragile"], "orbit views")
 
 
 @pytest.mark.parametrize("prec", ["f16", "bf16"])
@@ -358,10 +317,7 @@ def test_precision_mlp_tiny(torch, merf, tiny_scene, tiny_cams, prec):
     say(f"tiny, deferred MLP in {prec} on MFMA")
     gpu = gpu_render(torch, merf, tiny_scene, tiny_cams, mlp_prec=prec)
     ref, st = oracle.render(tiny_scene, tiny_cams)
-    p = psnr(gpu, ref)
-    err = np.abs(gpu - ref)
-    say(f"tiny {prec}: PSNR {p:.2f} dB  max|err| {err.max():.3e}  mean|err| {err.mean():.3e}")
-    assert p >= 45.0
+    check(gpu, ref, st["fragile"], f"tiny mlp {prec}", min_psnr=MIN_PSNR_DB)
     # alpha is untouched by the MLP precision
     f32 = gpu_render(torch, merf, tiny_scene, tiny_cams)
     assert np.array_equal(gpu[:, 3], f32[:, 3])
@@ -373,22 +329,15 @@ def test_precision_mlp_full_sampled(torch, merf, full_scene, prec):
     cams = synth.full_camera()
     gpu = gpu_render(torch, merf, full_scene, cams, mlp_prec=prec)
     ref, st = oracle.render(full_scene, cams, rows_stride=54, row_offset=7)
-    rows = np.arange(7, 1080, 54)
-    sel = (rows[:, None] * 1920 + np.arange(1920)[None, :]).reshape(-1)
-    p = psnr(gpu[sel], ref)
-    say(f"full {prec}: PSNR {p:.2f} dB  max|err| {np.abs(gpu[sel] - ref).max():.3e}")
-    assert p >= 45.0
+    check(gpu[rows_of(cams, 54, 7)], ref, st["fragile"], f"full mlp {prec}", min_psnr=MIN_PSNR_DB)
 
 
-@pytest.mark.parametrize("mlp", ["f16", "bf16"])
+@pytest.mark.parametrize("mlp", ["f32", "f16", "bf16"])
 def test_fp16_features_tiny(torch, merf, tiny_scene, tiny_cams, mlp):
     say(f"tiny, features dequantised to fp16, MLP {mlp}")
     gpu = gpu_render(torch, merf, tiny_scene, tiny_cams, feat_prec="f16", mlp_prec=mlp)
     ref, st = oracle.render(tiny_scene, tiny_cams)
-    p = psnr(gpu, ref)
-    ok = st["fragile"] == 0
-    say(f"tiny feat f16 + mlp {mlp}: PSNR {p:.2f} dB  max|err| non-fragile {np.abs(gpu - ref)[ok].max():.3e}")
-    assert p >= 45.0
+    check(gpu, ref, st["fragile"], f"tiny feat f16 mlp {mlp}", min_psnr=MIN_PSNR_DB)
 
 
 def test_fp16_features_full_sampled(torch, merf, full_scene):
@@ -396,25 +345,32 @@ def test_fp16_features_full_sampled(torch, merf, full_scene):
     cams = synth.full_camera()
     gpu = gpu_render(torch, merf, full_scene, cams, feat_prec="f16", mlp_prec="f16")
     ref, st = oracle.render(full_scene, cams, rows_stride=54, row_offset=7)
-    rows = np.arange(7, 1080, 54)
-    sel = (rows[:, None] * 1920 + np.arange(1920)[None, :]).reshape(-1)
-    p = psnr(gpu[sel], ref)
-    ok = st["fragile"] == 0
-    say(f"full feat f16: PSNR {p:.2f} dB  max|err| non-fragile {np.abs(gpu[sel] - ref)[ok].max():.3e}")
-    assert p >= 45.0
+    check(gpu[rows_of(cams, 54, 7)], ref, st["fragile"], "full feat f16 mlp f16", min_psnr=MIN_PSNR_DB)
 
 
-def test_planes_only_variant(torch, merf, tiny_scene, tiny_cams):
-    say("tiny scene without its 3D grid (planes only)")
+def test_precision_orbit_views_sampled(torch, merf, full_scene):
+    say("full scene, 16 orbit views at 480x270, every precision combination against the oracle")
+    cams = synth.orbit_cameras(16, w=480, h=270)
+    ref, st = oracle.render(full_scene, cams, rows_stride=9, row_offset=4)
+    sel = rows_of(cams, 9, 4)
+    for mlp, feat in (("f32", "f32"), ("f16", "f32"), ("bf16", "f32"), ("f16", "f16"), ("bf16", "f16")):
+        gpu = gpu_render(torch, merf, full_scene, cams, mlp_prec=mlp, feat_prec=feat)
+        check(gpu[sel], ref, st["fragile"], f"orbit mlp {mlp} feat {feat}", min_psnr=MIN_PSNR_DB)
+
+
+@pytest.mark.parametrize("feat", ["f32", "f16"])
+def test_planes_only_variant(torch, merf, tiny_scene, tiny_cams, feat):
+    say(f"tiny scene without its 3D grid (planes only), features {feat}")
     po = synth.planes_only(tiny_scene)
-    gpu = gpu_render(torch, merf, po, tiny_cams)
+    gpu = gpu_render(torch, merf, po, tiny_cams, feat_prec=feat)
     ref, st = oracle.render(po, tiny_cams)
-    check(gpu, ref, st["fragile"], "planes only")
+    check(gpu, ref, st["fragile"], f"planes only, features {feat}")
 
 
-def test_grid_only_variant(torch, merf, tiny_cams):
-    say("grid-only scene (L = 128, no planes)")
+@pytest.mark.parametrize("feat", ["f32", "f16"])
+def test_grid_only_variant(torch, merf, tiny_cams, feat):
+    say(f"grid-only scene (L = 128, no planes), features {feat}")
     go = synth.grid_only_scene(128, 0.08, seed=4)
-    gpu = gpu_render(torch, merf, go, tiny_cams)
+    gpu = gpu_render(torch, merf, go, tiny_cams, feat_prec=feat)
     ref, st = oracle.render(go, tiny_cams)
-    check(gpu, ref, st["fragile"], "grid only")
+    check(gpu, ref, st["fragile"], f"grid only, features {feat}")

@@ -8,8 +8,9 @@ import time
 import numpy as np
 import pytest
 
+import oracle
 import synth
-from scene_builders import dense_scene
+from gpu_helpers import MIN_PSNR_DB, check
 
 pytestmark = pytest.mark.gpu
 
@@ -85,6 +86,30 @@ def test_mix_equals_alone(torch, merf, scenes, use_graphs):
         for i in range(len(cams)):
             alone = render_alone(torch, merf, scenes[scene_of[i]], cams, i, prec[i])
             assert np.array_equal(outs[i].cpu().numpy(), alone), i
+    finally:
+        srv.close()
+
+
+def test_served_outputs_match_oracle(torch, merf, scenes):
+    say("serving: 24 uneven requests over 3 scenes (fp32 / fp16 / bf16 MLP) against the FP64 oracle")
+    cams, scene_of, prec = request_mix(24, seed=13)
+    arr = merf.camera_array(cams)
+    srv = merf.Server(slots=3, max_batch=8, use_graphs=True)
+    try:
+        ids = [srv.add_scene(s) for s in scenes]
+        outs = [torch.full((int(w) * int(h), 4), float("nan"), device="cuda") for w, h in cams.size]
+        torch.cuda.synchronize()
+        tickets = [srv.submit(ids[scene_of[i]], arr, i, outs[i].data_ptr(), merf.render_params(mlp_prec=prec[i]))
+                   for i in range(len(cams))]
+        for t in tickets:
+            srv.wait(t)
+        for k in range(3):
+            idx = [i for i in range(len(cams)) if scene_of[i] == k]
+            sub = cams.subset(idx)
+            ref, st = oracle.render(scenes[k], sub)
+            gpu = np.concatenate([outs[i].cpu().numpy().astype(np.float64) for i in idx])
+            check(gpu, ref, st["fragile"], f"served scene {k}: {len(idx)} requests", max_fragile=0.01,
+                  min_psnr=MIN_PSNR_DB)
     finally:
         srv.close()
 
