@@ -164,6 +164,25 @@ int merf_render(merf_scene_t s, const merf_camera *cams, int32_t n_cams, const m
                 float *out_rgba_dev, void *hip_stream);
 
 /*
+ * merf_render for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, image and errors as merf_render, bit for bit, but it calls
+ * no hipMalloc, hipFree or other allocating routine, and every kernel runs on
+ * hip_stream (merf_render runs the tile-order prepass on a stream of the
+ * library's own, with work buffers it allocates).  The tile-order prepass
+ * instead uses one fixed device array of 672 KiB per GPU, held until the
+ * process ends, which bounds a launch run in tile order (tile_order 0) to
+ * 131072 8x8 tiles (four 1920x1080 frames): a call with such a launch is
+ * rejected with MERF_E_INVALID before anything runs (tile_order 1 has no
+ * bound).  Every call on a GPU shares that GPU's array; each launch rewrites
+ * all of it that it reads, so nothing carries over from an earlier call, but
+ * calls that overlap on one GPU (different streams) race and must not be
+ * issued.  hip_stream must belong to the current device.
+ */
+int merf_render_noalloc(merf_scene_t s, const merf_camera *cams, int32_t n_cams, const merf_render_params *p,
+                        float *out_rgba_dev, void *hip_stream);
+
+/*
  * Release a scene.  Waits for all work queued on the device before freeing.
  * Errors: MERF_E_INVALID for NULL, an unknown handle or a second free.
  */

@@ -601,6 +601,123 @@ int merf_render(merf_scene_t s, const merf_camera *cams, int32_t n_cams, const m
     return MERF_OK;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Render without allocating (merf_render_noalloc).  The tile-order work
+// buffers of merf_render are hipMalloc'd on first use; here they are one fixed
+// device array of this file, and every kernel runs on the caller's stream
+// (no stream, event or buffer of the library's own).  Each device holds its
+// own copy of the array at its own address, looked up once per device.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kFixedKeys = kOrderMaxTiles;                               // uint8 cost keys
+constexpr size_t kFixedCounts = sizeof(uint32_t) * (kOrderMaxTiles / 16);   // key counts per group of 16 tiles
+constexpr size_t kFixedOrder = sizeof(int32_t) * kOrderMaxTiles;            // the order
+constexpr size_t kFixedBytes = kFixedKeys + kFixedCounts + kFixedOrder;     // 672 KiB
+static_assert(kFixedKeys % 256 == 0 && kFixedCounts % 256 == 0, "sub-buffer alignment");
+
+constexpr int kMaxDevices = 64;
+std::mutex g_fixed_mutex;
+uint8_t *g_fixed_ptr[kMaxDevices] = {};     // device address of `scratch` per device ordinal, once looked up
+
+}  // namespace
+
+static __device__ __align__(256) uint8_t scratch[kFixedBytes];
+
+namespace {
+
+// Device address of this device's `scratch`.  The array's name is a host-side
+// stand-in; kernels get this address.  Called with the device current.
+int fixed_scratch(int device, uint8_t **out) {
+    if (device < 0 || device >= kMaxDevices) return fail(MERF_E_INVALID, "device %d out of range", device);
+    std::lock_guard<std::mutex> lk(g_fixed_mutex);
+    if (!g_fixed_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress");
+        g_fixed_ptr[device] = static_cast<uint8_t *>(p);
+    }
+    *out = g_fixed_ptr[device];
+    return MERF_OK;
+}
+
+// Tiles of the launch that starts at camera `first` (the same packing as
+// add_camera: up to kCamsPerLaunch cameras); advances first.
+int64_t next_launch_tiles(const merf_camera *cams, int32_t n_cams, int &first) {
+    int64_t tiles = 0;
+    for (int k = 0; k < kCamsPerLaunch && first < n_cams; ++k, ++first)
+        tiles += (int64_t)((cams[first].width + kTile - 1) / kTile) * ((cams[first].height + kTile - 1) / kTile);
+    return tiles;
+}
+
+}  // namespace
+
+extern "C" {
+
+int merf_render_noalloc(merf_scene_t s, const merf_camera *cams, int32_t n_cams, const merf_render_params *p,
+                        float *out_rgba_dev, void *hip_stream) {
+    clear_error();
+    if (!live(s)) return fail(MERF_E_INVALID, "merf_render_noalloc: invalid scene handle");
+    float step = 0.0f;
+    int rc = check_params(p, s->ds.res, &step);
+    if (rc) return rc;
+    if (n_cams < 0) return fail(MERF_E_INVALID, "n_cams %d < 0", n_cams);
+    if (n_cams == 0) return MERF_OK;
+    if (!cams) return fail(MERF_E_INVALID, "cams is NULL");
+    if (!out_rgba_dev) return fail(MERF_E_INVALID, "output buffer is NULL");
+    for (int i = 0; i < n_cams; ++i)
+        if ((rc = check_camera(cams[i], i))) return rc;
+    // every launch that would run in tile order must fit the fixed buffers;
+    // checked before anything is launched
+    const bool ordered = p->tile_order == 0;
+    if (ordered) {
+        for (int first = 0; first < n_cams;) {
+            const int at = first;
+            const int64_t tiles = next_launch_tiles(cams, n_cams, first);
+            if (tiles > kOrderMaxTiles)
+                return fail(MERF_E_INVALID,
+                            "merf_render_noalloc: the launch of cameras %d..%d has %lld tiles, more than the "
+                            "%d its fixed tile-order buffers hold (use tile_order 1 or fewer cameras per call)",
+                            at, first - 1, (long long)tiles, kOrderMaxTiles);
+        }
+    }
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    int device = -1;
+    hipError_t e = hipGetDevice(&device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    hipDevice_t sdev = device;
+    if (stream && (e = hipStreamGetDevice(stream, &sdev)) != hipSuccess) return hip_fail(e, "hipStreamGetDevice");
+    if (sdev != device)
+        return fail(MERF_E_INVALID, "merf_render_noalloc: the stream belongs to device %d, the current device is %d",
+                    (int)sdev, device);
+    uint8_t *fixed = nullptr;
+    if (ordered && (rc = fixed_scratch(device, &fixed))) return rc;
+    int64_t pix = 0;
+    for (int first = 0; first < n_cams;) {
+        RenderBatch rb;
+        begin_batch(rb, *p, step);
+        while (first < n_cams && add_camera(rb, cams[first], out_rgba_dev + pix * 4)) {
+            pix += (int64_t)cams[first].width * cams[first].height;
+            ++first;
+        }
+        if (rb.n_cams == 0) return fail(MERF_E_INVALID, "camera %d alone exceeds one launch", first);
+        if (ordered && rb.total_tiles >= kOrderMinTiles) {
+            // the prepass writes every key, group count and order entry the
+            // launch reads, so nothing left by an earlier call needs clearing
+            uint8_t *keys = fixed;
+            uint32_t *counts = reinterpret_cast<uint32_t *>(fixed + kFixedKeys);
+            int32_t *order = reinterpret_cast<int32_t *>(fixed + kFixedKeys + kFixedCounts);
+            if ((e = launch_tile_order(s->ds, rb, keys, counts, order, stream)) != hipSuccess)
+                return hip_fail(e, "tile order");
+            rb.order = order;
+        }
+        if ((e = launch_render(s->ds, rb, stream)) != hipSuccess) return hip_fail(e, "render launch");
+    }
+    return MERF_OK;
+}
+
 int merf_dequantize(const uint8_t *codes_dev, int64_t n, float m, int32_t prec, void *out_dev, void *hip_stream) {
     clear_error();
     if (n < 0) return fail(MERF_E_INVALID, "n %lld < 0", (long long)n);

@@ -52,9 +52,9 @@ class merf_render_params(C.Structure):
                 ("skip_mode", C.c_int32), ("tile_order", C.c_int32), ("stats_dev", C.c_void_p)]
 
 
-EXPORTS = ["merf_scene_upload", "merf_render", "merf_free", "merf_last_error", "merf_set_hbm_budget",
-           "merf_hbm_in_use", "merf_scene_bytes", "merf_dequantize", "merf_occupancy_pyramid",
-           "merf_distance_grid", "merf_octant_extent_grid"]
+EXPORTS = ["merf_scene_upload", "merf_render", "merf_render_noalloc", "merf_free", "merf_last_error",
+           "merf_set_hbm_budget", "merf_hbm_in_use", "merf_scene_bytes", "merf_dequantize",
+           "merf_occupancy_pyramid", "merf_distance_grid", "merf_octant_extent_grid"]
 
 _lib = None
 
@@ -72,6 +72,8 @@ def load(path: str = LIB_PATH):
     lib.merf_render.argtypes = [C.c_void_p, C.POINTER(merf_camera), C.c_int32, C.POINTER(merf_render_params),
                                 C.c_void_p, C.c_void_p]
     lib.merf_render.restype = C.c_int
+    lib.merf_render_noalloc.argtypes = lib.merf_render.argtypes
+    lib.merf_render_noalloc.restype = C.c_int
     lib.merf_free.argtypes = [C.c_void_p]
     lib.merf_free.restype = C.c_int
     lib.merf_last_error.argtypes = []
@@ -202,6 +204,13 @@ def merf_render(handle: int, cam_arr, n_cams: int, params: merf_render_params, o
     """Raw merf_render: cam_arr from camera_array(), out_ptr a device pointer."""
     _check(load().merf_render(C.c_void_p(handle), cam_arr, int(n_cams), C.byref(params), C.c_void_p(out_ptr),
                               C.c_void_p(stream_ptr)))
+
+
+def merf_render_noalloc(handle: int, cam_arr, n_cams: int, params: merf_render_params, out_ptr: int,
+                        stream_ptr: int = 0):
+    """Raw merf_render_noalloc (same arguments as merf_render)."""
+    _check(load().merf_render_noalloc(C.c_void_p(handle), cam_arr, int(n_cams), C.byref(params),
+                                      C.c_void_p(out_ptr), C.c_void_p(stream_ptr)))
 
 
 def merf_dequantize(codes_ptr: int, n: int, m: float, prec: int, out_ptr: int, stream_ptr: int = 0):
