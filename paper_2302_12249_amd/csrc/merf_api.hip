@@ -25,6 +25,7 @@ struct merf_scene {
     size_t dev_bytes;
     DevScene ds;
     int32_t nbricks;
+    bool ordered;           // allocated stream-ordered (scene_upload_on)
 };
 
 namespace merf {
@@ -412,12 +413,29 @@ size_t merf_hbm_in_use(void) {
 
 size_t merf_scene_bytes(merf_scene_t s) { return live(s) ? s->dev_bytes : 0; }
 
-int merf_scene_upload(const merf_scene_desc *desc, merf_scene_t *out) {
+}  // extern "C"
+
+namespace {
+
+// Device allocation of an upload: plain (hipMalloc / hipFree, which waits for
+// the device) or stream-ordered on `stream` (hipMallocAsync / hipFreeAsync,
+// which wait for nothing but that stream's earlier work).
+hipError_t dev_alloc(void **p, size_t n, bool ordered, hipStream_t stream) {
+    return ordered ? hipMallocAsync(p, n, stream) : hipMalloc(p, n);
+}
+hipError_t dev_free(void *p, bool ordered, hipStream_t stream) {
+    return ordered ? hipFreeAsync(p, stream) : hipFree(p);
+}
+
+// merf_scene_upload (ordered = false: null stream, plain allocation) and
+// scene_upload_on (ordered = true: everything on stream).
+int upload_impl(const merf_scene_desc *desc, merf_scene_t *out, bool ordered, hipStream_t stream) {
     clear_error();
     if (!out) return fail(MERF_E_INVALID, "output handle pointer is NULL");
     *out = nullptr;
     int rc = validate_desc(desc);
     if (rc) return rc;
+    if (!ordered) stream = nullptr;
 
     const int64_t nbricks = count_bricks(desc);
     if ((nbricks + 1) * (int64_t)kBrickBytes >= (int64_t)1 << 31)
@@ -452,11 +470,13 @@ int merf_scene_upload(const merf_scene_desc *desc, merf_scene_t *out) {
     const size_t s_dist1 = s_dist0 + align_up(nf, 256),
                  staging = s_dist1 + align_up(octants ? nf * sizeof(int32_t) : nf, 256);
     void *base = nullptr, *stage = nullptr;
-    hipError_t e = hipMalloc(&base, total);
-    if (e == hipSuccess) e = hipMalloc(&stage, staging);
+    hipError_t e = dev_alloc(&base, total, ordered, stream);
+    if (e == hipSuccess) e = dev_alloc(&stage, staging, ordered, stream);
+    if (e == hipSuccess && ordered) e = hipStreamSynchronize(stream);   // allocation failures surface here
     if (e != hipSuccess || !base || !stage) {
         (void)hipGetLastError();
-        if (base) (void)hipFree(base);
+        if (base) (void)dev_free(base, ordered, stream);
+        if (base && ordered) (void)hipStreamSynchronize(stream);
         release();
         return fail(MERF_E_OOM, "hipMalloc (%zu + %zu staging bytes) failed: %s", total, staging, hipGetErrorString(e));
     }
@@ -477,13 +497,14 @@ int merf_scene_upload(const merf_scene_desc *desc, merf_scene_t *out) {
     }
     for (const Copy &c : copies) {
         if (c.n == 0) continue;
-        e = hipMemcpy(c.dst, c.src, c.n, hipMemcpyHostToDevice);
+        e = ordered ? hipMemcpyAsync(c.dst, c.src, c.n, hipMemcpyHostToDevice, stream)
+                    : hipMemcpy(c.dst, c.src, c.n, hipMemcpyHostToDevice);
         if (e != hipSuccess) break;
     }
-    if (e == hipSuccess && R == 0) e = hipMemset(dev(o_planes), 0, (size_t)3 * 2 * 2 * kChannels);
+    if (e == hipSuccess && R == 0) e = hipMemsetAsync(dev(o_planes), 0, (size_t)3 * 2 * 2 * kChannels, stream);
     if (e == hipSuccess)
         e = launch_pack_bricks(stg(s_blocks), reinterpret_cast<const int32_t *>(stg(s_index)),
-                               reinterpret_cast<const int32_t *>(stg(s_pos)), (int)nbricks, L, dev(o_bricks), nullptr);
+                               reinterpret_cast<const int32_t *>(stg(s_pos)), (int)nbricks, L, dev(o_bricks), stream);
     if (e == hipSuccess) {
         OccLevels lv{};
         lv.n = desc->occ_levels;
@@ -492,13 +513,14 @@ int merf_scene_upload(const merf_scene_desc *desc, merf_scene_t *out) {
             lv.res[l] = desc->occ_res[l];
         }
         e = octants ? launch_octant_extents(lv, stg(s_dist0), reinterpret_cast<int32_t *>(stg(s_dist1)),
-                                            dev(lay.dist), nullptr)
-                    : launch_distance_grid(lv, stg(s_dist0), stg(s_dist1), dev(lay.dist), nullptr);
+                                            dev(lay.dist), stream)
+                    : launch_distance_grid(lv, stg(s_dist0), stg(s_dist1), dev(lay.dist), stream);
     }
-    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
-    (void)hipFree(stage);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    (void)dev_free(stage, ordered, stream);
     if (e != hipSuccess) {
-        (void)hipFree(base);
+        (void)dev_free(base, ordered, stream);
+        if (ordered) (void)hipStreamSynchronize(stream);
         release();
         return hip_fail(e, "scene upload");
     }
@@ -508,6 +530,7 @@ int merf_scene_upload(const merf_scene_desc *desc, merf_scene_t *out) {
     s->dev_base = base;
     s->dev_bytes = total;
     s->nbricks = (int32_t)nbricks;
+    s->ordered = ordered;
     DevScene &ds = s->ds;
     ds.brick_index = reinterpret_cast<const int32_t *>(dev(o_bidx));
     ds.bricks = dev(o_bricks);
@@ -553,19 +576,46 @@ int merf_scene_upload(const merf_scene_desc *desc, merf_scene_t *out) {
     return MERF_OK;
 }
 
+// Forget a live scene and return its memory to the budget; false if s is
+// not live.
+bool unregister(merf_scene_t s) {
+    std::lock_guard<std::mutex> lk(g_mutex);
+    if (!s || !g_live.count(s)) return false;
+    g_live.erase(s);
+    g_in_use -= s->dev_bytes;
+    return true;
+}
+
+}  // namespace
+
+namespace merf {
+
+int scene_upload_on(const merf_scene_desc *desc, hipStream_t stream, merf_scene_t *out) {
+    return upload_impl(desc, out, true, stream);
+}
+
+int scene_release_on(merf_scene_t s, hipStream_t stream) {
+    clear_error();
+    if (!unregister(s)) return fail(MERF_E_INVALID, "scene_release_on: unknown or already freed scene handle");
+    const hipError_t e = dev_free(s->dev_base, s->ordered, stream);
+    s->magic = 0;
+    delete s;
+    if (e != hipSuccess) return hip_fail(e, "scene release");
+    return MERF_OK;
+}
+
+}  // namespace merf
+
+extern "C" {
+
+int merf_scene_upload(const merf_scene_desc *desc, merf_scene_t *out) { return upload_impl(desc, out, false, nullptr); }
+
 int merf_free(merf_scene_t s) {
     clear_error();
-    {
-        std::lock_guard<std::mutex> lk(g_mutex);
-        if (!s || !g_live.count(s)) return fail(MERF_E_INVALID, "merf_free: unknown or already freed scene handle");
-        g_live.erase(s);
-    }
+    if (!unregister(s)) return fail(MERF_E_INVALID, "merf_free: unknown or already freed scene handle");
     hipError_t e1 = hipDeviceSynchronize();
-    hipError_t e2 = hipFree(s->dev_base);
-    {
-        std::lock_guard<std::mutex> lk(g_mutex);
-        g_in_use -= s->dev_bytes;
-    }
+    hipError_t e2 = dev_free(s->dev_base, s->ordered, nullptr);
+    if (e2 == hipSuccess && s->ordered) e2 = hipStreamSynchronize(nullptr);
     s->magic = 0;
     delete s;
     if (e1 != hipSuccess) return hip_fail(e1, "hipDeviceSynchronize (merf_free)");

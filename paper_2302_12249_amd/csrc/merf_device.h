@@ -110,6 +110,33 @@ struct RenderBatch {
     DevCamera cams[kCamsPerLaunch];
 };
 
+// Served launches (merf_serve.hip): one persistent launch renders requests
+// of several resident scenes.  The descriptors live in device memory, so a
+// captured graph replays a launch unchanged (its first node copies the
+// descriptors in).
+struct ServeWork {
+    DevCamera cam;                               // tile_start: first tile of this request in the launch
+    int32_t scene;                               // slot of its scene in the server's scene table
+    float step, inv_step, t_min;
+    int32_t delta_mode;
+};
+struct ServeLaunch {
+    int32_t n_work, total_tiles;
+    ServeWork work[kCamsPerLaunch];
+};
+// Workgroup b of a served launch of G workgroups takes tiles from the share
+// of XCD x = b % 8 (the runs of 4 consecutive tiles that xcd_remap deals to
+// that XCD): first position b / 8, then G / 8 + the positions it takes from
+// the XCD's counter, until the share is exhausted.  Each counter has a
+// 256-byte line of its own.  Zero before a slot's first launch; every launch
+// leaves it zero.
+constexpr int kXcds = 8;
+constexpr int kCtlStride = 64;                   // uint32 per counter line
+struct ServeCtl {
+    uint32_t next[kXcds * kCtlStride];           // next[x * kCtlStride]: positions taken by XCD x
+    uint32_t done[kCtlStride];                   // done[0]: workgroups finished
+};
+
 // Slots of RenderBatch::phases (uint64 each, summed over the waves of a launch).
 enum PhaseSlot {
     kPhSetup = 0,        // cycles: ray set-up and the first segment
@@ -130,6 +157,13 @@ enum PhaseSlot {
 
 // Launchers (merf_render.hip).
 hipError_t launch_render(const DevScene &sc, const RenderBatch &rb, hipStream_t stream);
+// Served launch: grid workgroups (a multiple of kXcds) render the tiles of
+// *launch (device) with the scenes of table (device, indexed by
+// ServeWork::scene), in the kernel variant of (mlp_prec, feat_prec,
+// skip_mode); ctl (device) is the slot's control block.
+const void *served_kernel(int mlp_prec, int feat_prec, int skip_mode);
+hipError_t launch_render_served(const DevScene *table, const ServeLaunch *launch, ServeCtl *ctl, int mlp_prec,
+                                int feat_prec, int skip_mode, int grid, hipStream_t stream);
 // Heaviest-first tile order of a launch: keys (uint8 [kOrderMaxTiles])
 // receive the cost keys, group_counts (uint32 [kOrderMaxTiles / 16]) their
 // counts per group of tiles, order (int32 [total_tiles]) the tiles sorted by

@@ -21,6 +21,15 @@ void clear_error();
 // that entry point runs is the renderer's own with the renderer's constant.
 inline float eq8_scale(float m) { return (2.0f * m) / 255.0f; }
 
+// Upload for the serving runtime: merf_scene_upload with every allocation,
+// copy and kernel ordered on `stream` (stream-ordered allocation, so nothing
+// waits for other work on the device); returns once the scene is resident.
+int scene_upload_on(const merf_scene_desc *desc, hipStream_t stream, merf_scene_t *out);
+// Release a scene of scene_upload_on, in order on `stream`, without waiting
+// for other work on the device: the caller guarantees that no queued or
+// running work reads it.
+int scene_release_on(merf_scene_t s, hipStream_t stream);
+
 // Device view of a live scene handle, or nullptr.
 const DevScene *scene_dev(merf_scene_t s);
 

@@ -242,7 +242,11 @@ struct Footprint {
     float fx, fy, fz;   // grid voxel fractions
 };
 
-__device__ __forceinline__ Footprint footprint(const DevScene &sc, float3 p) {
+// Scene accessors take the scene as S = const DevScene (a kernel argument)
+// or as a constant-address-space DevScene (a slot of a served launch's
+// table), so both read it with scalar loads that may be repeated at will.
+template <typename S>
+__device__ __forceinline__ Footprint footprint(const S &sc, float3 p) {
     Footprint f;
     // ---- three planes, bilinear: P_x(y, z), P_y(x, z), P_z(x, y)
     const float ps = sc.p_scale, ps2 = sc.p_off, pmax = sc.p_max;
@@ -280,7 +284,8 @@ struct Texels {
 // the alpha test, and places one wait before it.  Every array is present on
 // the device (a scene without a grid or without planes reads an all-zero
 // stand-in), so nothing here branches.
-__device__ __forceinline__ Texels gather(const DevScene &sc, const Footprint &f) {
+template <typename S>
+__device__ __forceinline__ Texels gather(const S &sc, const Footprint &f) {
     Texels x;
     const int brick = load_at<int>(reinterpret_cast<const uint8_t *>(sc.brick_index), f.bi * 4u);
 #pragma unroll
@@ -309,8 +314,8 @@ struct SampleResult {
 // One evaluated sample: gather, dequantise, decode.
 // All offsets are 32-bit (the upload keeps every array below 2 GiB) and are
 // added to uniform base pointers, so no 64-bit address arithmetic runs per lane.
-template <bool kFeatF16>
-__device__ __forceinline__ SampleResult eval_sample(const DevScene &sc, float3 p, float delta) {
+template <bool kFeatF16, typename S>
+__device__ __forceinline__ SampleResult eval_sample(const S &sc, float3 p, float delta) {
     const Footprint f = footprint(sc, p);
     const Texels x = gather(sc, f);
     // texel words of the 20 texels (lo = channels 0..3, hi = 4..7) and their
@@ -497,7 +502,8 @@ __device__ __forceinline__ void open_segment(float3 o, float3 d, float ta, int r
 // corner at that cell, extending the way the segment travels, is empty; 0
 // means the cell is occupied (the cube is the cell itself).  ue is the
 // segment parameter at which the cube ends (slab test).
-__device__ __forceinline__ int dist_lookup(const DevScene &sc, const Segment &s, float3 p, float &ue) {
+template <typename S>
+__device__ __forceinline__ int dist_lookup(const S &sc, const Segment &s, float3 p, float &ue) {
     const int r = sc.dist_res;
     // cell of p: (p + 2) r / 4 rounded down; contracted points have p >= -2
     // up to rounding, so truncation equals the floor and no lower clamp is
@@ -615,9 +621,9 @@ __device__ __forceinline__ floatx4 mfma16(half4_t<kPrec> a, half4_t<kPrec> b, fl
 // Returns h(x) for this lane's pixel.  All 64 lanes must call it.
 template <int kPrec>
 __device__ __forceinline__ float3 deferred_mlp_mfma(const float *__restrict__ W, float *xs, const Accum &acc,
-                                                    float3 d) {
+                                                    float3 d, int lane) {
     using Lds = MlpLds<kPrec>;
-    const int lane = (int)threadIdx.x, j = lane & 15, g = lane >> 4;
+    const int j = lane & 15, g = lane >> 4;
     const float *W0 = W, *b0 = W0 + kMlpIn * kMlpHidden, *W1 = b0 + kMlpHidden, *b1 = W1 + kMlpHidden * kMlpHidden,
                 *W2 = b1 + kMlpHidden, *b2 = W2 + kMlpHidden * kMlpOut;
     // Weights and biases first, so their loads overlap the input encoding.
@@ -736,22 +742,32 @@ constexpr int kLdsFloats = MlpLds<kPrec>::kFloats > kParkFloats ? MlpLds<kPrec>:
 // (skip_mode 1) instead of the distance grid (skip_mode 0).
 // kMode: 0 renders; 1 also adds the statistics counters (and records the
 // gathers when rb.rec is set); 2 also takes the phase profile.
-template <int kMode, int kMlpPrec, bool kFeatF16, bool kLevels>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_render(const DevScene sc, const RenderBatch rb) {
+// March parameters of one tile's rays.
+struct TileParams {
+    float step, istep, t_min;
+    int32_t delta_mode;
+};
+
+// Measurement outputs of the statistics variants (kMode >= 1); see RenderBatch.
+struct MeasureArgs {
+    unsigned long long *stats;
+    uint32_t *rec;
+    int32_t *rec_count;
+    int32_t rec_cap, total_tiles;
+    unsigned long long *phases;
+};
+
+// One wave renders local tile lt of camera cam (launch tile `tile`, used by
+// the measurement outputs only) of scene sc; lane = threadIdx.x.
+template <int kMode, int kMlpPrec, bool kFeatF16, bool kLevels, typename S, typename Cam>
+__device__ __forceinline__ void render_tile(const S &sc, const Cam &cam, int lt, int tile,
+                                            const TileParams tp, const MeasureArgs ma, float *lds, const int lane) {
     constexpr bool kStats = kMode >= 1, kPhase = kMode == 2;
-    __shared__ float lds[kLdsFloats<kMlpPrec>];
-    const int slot = xcd_remap((int)blockIdx.x, rb.total_tiles);
-    int tile = rb.order ? rb.order[slot] : slot;
-    if ((unsigned)tile >= (unsigned)rb.total_tiles) tile = slot;   // never leave the launch
-    int c = 0;
-#pragma unroll
-    for (int i = 1; i < kCamsPerLaunch; ++i)
-        if (i < rb.n_cams && tile >= rb.cams[i].tile_start) c = i;
-    const DevCamera &cam = rb.cams[c];
-    const int lt = tile - cam.tile_start;
-    const int lane = (int)threadIdx.x;
-    const int px = (lt % cam.tiles_x) * kTile + (lane & (kTile - 1));
-    const int py = (lt / cam.tiles_x) * kTile + (lane / kTile);
+    // the tile's corner is uniform: kept in scalar registers
+    const int tx0 = __builtin_amdgcn_readfirstlane((lt % cam.tiles_x) * kTile);
+    const int ty0 = __builtin_amdgcn_readfirstlane((lt / cam.tiles_x) * kTile);
+    const int px = tx0 + (lane & (kTile - 1));
+    const int py = ty0 + (lane / kTile);
     const bool active = px < cam.width && py < cam.height;
     PhaseClock<kPhase> ph;
     ph.start();
@@ -768,7 +784,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 
     Counters cnt = {0u, 0u, 0u, 0u, 0u};
     Accum acc = {1.0f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    const float step = rb.step, istep = rb.inv_step;
+    const float step = tp.step, istep = tp.istep;
     Segment s;
     {
         const Candidates C = make_candidates(o, d);
@@ -884,7 +900,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
             }
             if (empty < 0) {
                 float delta = u1 - u0;
-                if (rb.delta_mode == 1) {
+                if (tp.delta_mode == 1) {
                     float3 y0 = make_float3(fmaf(u0, s.e.x, s.A.x), fmaf(u0, s.e.y, s.A.y), fmaf(u0, s.e.z, s.A.z));
                     float3 y1 = (s.k == s.n - 1)
                                     ? segment_end(o, d, s.tb, s.reg)
@@ -946,14 +962,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
             before += __popcll(__ballot(pc > j));
             if (j < pc && item < 64 && !terminated) {
                 const int e = j * 64 + lane;
-                if (kStats && rb.rec) {
+                if (kStats && ma.rec) {
                     // measurement: record the texel offsets of this sample
                     const uint32_t k = cnt.evaluated;
-                    if (k < (uint32_t)rb.rec_cap) {
+                    if (k < (uint32_t)ma.rec_cap) {
                         const float4 q = pq[e];
                         const Footprint f = footprint(sc, make_float3(q.x, q.y, q.z));
                         const uint32_t qs = (uint32_t)tile * 64u + (uint32_t)lane;
-                        *reinterpret_cast<u32x4 *>(rb.rec + 4 * ((size_t)k * (size_t)rb.total_tiles * 64u + qs)) =
+                        *reinterpret_cast<u32x4 *>(ma.rec + 4 * ((size_t)k * (size_t)ma.total_tiles * 64u + qs)) =
                             u32x4{f.op[0], f.op[1], f.op[2], (f.bi << 13) | f.ol};
                     }
                 }
@@ -961,7 +977,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
                 const SampleResult r = {ra.x, {ra.y, ra.z, ra.w, rbv.x, rbv.y, rbv.z, rbv.w}};
                 composite<kStats>(acc, r, cnt);
                 ++done;
-                if (acc.T < rb.t_min) {          // early termination (Sec. 6)
+                if (acc.T < tp.t_min) {          // early termination (Sec. 6)
                     alive = false;
                     terminated = true;
                 }
@@ -980,19 +996,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
         if (kPhase) ph.lap(kPhComposite);
     }
 
-    const float3 h = deferred_mlp_mfma<kMlpPrec>(sc.mlp, lds, acc, d);
+    const float3 h = deferred_mlp_mfma<kMlpPrec>(sc.mlp, lds, acc, d, lane);
     if (active) {
         // the pixel again from the lane id (an opaque copy, so the compiler
         // recomputes it instead of holding px and py through the march)
         int l2 = lane;
         asm volatile("" : "+v"(l2));
-        const int ox = (lt % cam.tiles_x) * kTile + (l2 & (kTile - 1));
-        const int oy = (lt / cam.tiles_x) * kTile + (l2 / kTile);
+        const int ox = tx0 + (l2 & (kTile - 1));
+        const int oy = ty0 + (l2 / kTile);
         float4 rgba = make_float4(acc.cd0 + h.x, acc.cd1 + h.y, acc.cd2 + h.z, 1.0f - acc.T);
         *reinterpret_cast<float4 *>(cam.out + ((int64_t)oy * cam.width + ox) * 4) = rgba;
     }
     if (kPhase) ph.lap(kPhMlp);
-    if (kStats && rb.rec_count) rb.rec_count[tile * 64 + lane] = (int32_t)cnt.evaluated;
+    if (kStats && ma.rec_count) ma.rec_count[tile * 64 + lane] = (int32_t)cnt.evaluated;
     if (kStats) {
         unsigned long long v[6] = {active ? 1ull : 0ull, cnt.occ_lookups, cnt.visited, cnt.evaluated, cnt.contributing,
                                    terminated ? 1ull : 0ull};
@@ -1001,7 +1017,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
             unsigned long long x = v[i];
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-            if (lane == 0 && x) atomicAdd(rb.stats + i, x);
+            if (lane == 0 && x) atomicAdd(ma.stats + i, x);
         }
         if (kPhase) {
             ph.count(kPhWaves);
@@ -1009,7 +1025,89 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
             ph.count(kPhOpenLanes, x);
-            if (lane < kPhSlots && ph.v) atomicAdd(rb.phases + lane, (unsigned long long)ph.v);
+            if (lane < kPhSlots && ph.v) atomicAdd(ma.phases + lane, (unsigned long long)ph.v);
+        }
+    }
+}
+
+template <int kMode, int kMlpPrec, bool kFeatF16, bool kLevels>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_render(const DevScene sc, const RenderBatch rb) {
+    __shared__ float lds[kLdsFloats<kMlpPrec>];
+    const int slot = xcd_remap((int)blockIdx.x, rb.total_tiles);
+    int tile = rb.order ? rb.order[slot] : slot;
+    if ((unsigned)tile >= (unsigned)rb.total_tiles) tile = slot;   // never leave the launch
+    int c = 0;
+#pragma unroll
+    for (int i = 1; i < kCamsPerLaunch; ++i)
+        if (i < rb.n_cams && tile >= rb.cams[i].tile_start) c = i;
+    const DevCamera &cam = rb.cams[c];
+    const TileParams tp = {rb.step, rb.inv_step, rb.t_min, rb.delta_mode};
+    const MeasureArgs ma = {rb.stats, rb.rec, rb.rec_count, rb.rec_cap, rb.total_tiles, rb.phases};
+    render_tile<kMode, kMlpPrec, kFeatF16, kLevels>(sc, cam, tile - cam.tile_start, tile, tp, ma, lds,
+                                                    (int)threadIdx.x);
+}
+
+// Served launch (persistent): each workgroup takes tiles from its XCD's
+// share of the launch (XCD x = blockIdx % 8 holds the runs of kXcdChunk
+// consecutive tiles that xcd_remap deals to x) until the share is exhausted,
+// so neighbouring tiles still share an L2 and the launch shape does not
+// depend on the requests.  A workgroup's first tile is fixed by its index;
+// it asks the XCD's counter for the next one as it starts each tile, so the
+// atomic's round trip overlaps the render.  Each tile belongs to one request,
+// which names its camera, march parameters and scene (a slot of the server's
+// scene table).  The last workgroup to finish zeroes the control block for
+// the next launch.
+typedef const __attribute__((address_space(4))) DevScene ConstScene;
+typedef const __attribute__((address_space(4))) ServeLaunch ConstLaunch;
+typedef const __attribute__((address_space(4))) ServeWork ConstWork;
+
+__device__ __forceinline__ int xcd_share_tile(int x, uint32_t i) {
+    return (int)((((i / kXcdChunk) * kXcds + (uint32_t)x) * kXcdChunk) + i % kXcdChunk);
+}
+
+// The scene table and the launch descriptors are read through the constant
+// address space: they do not change during the launch, so the compiler reads
+// them with scalar loads and may repeat a load instead of holding its value.
+template <int kMlpPrec, bool kFeatF16, bool kLevels>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_render_served(
+    ConstScene *__restrict__ table, ConstLaunch *__restrict__ launch, ServeCtl *__restrict__ ctl) {
+    __shared__ float lds[kLdsFloats<kMlpPrec>];
+    const int x = (int)(blockIdx.x % kXcds);
+    const uint32_t base = gridDim.x / kXcds;      // positions handed out by workgroup index
+    uint32_t *counter = ctl->next + x * kCtlStride;
+    uint32_t i = blockIdx.x / kXcds;
+    for (;;) {
+        // nothing is carried from one tile to the next: opaque copies of the
+        // lane id and the launch pointer keep the compiler from hoisting
+        // lane-only address arithmetic and descriptor loads out of this loop
+        // and holding them in registers through every tile
+        // (the lane id is recomputed from the exec mask: a workgroup is one wave)
+        int lane = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+        ConstLaunch *L = launch;
+        asm volatile("" : "+v"(lane), "+s"(L));
+        const int n = L->total_tiles, nw = L->n_work;
+        const int tile = xcd_share_tile(x, i);
+        if (i >= (uint32_t)n || tile >= n) break;
+        uint32_t nx = 0;                           // the next position, in flight during the render
+        if (lane == 0) nx = base + atomicAdd(counter, 1u);
+        int c = 0;
+#pragma unroll
+        for (int k = 1; k < kCamsPerLaunch; ++k)
+            if (k < nw && tile >= L->work[k].cam.tile_start) c = k;
+        ConstWork &w = L->work[c];
+        const TileParams tp = {w.step, w.inv_step, w.t_min, w.delta_mode};
+        const MeasureArgs ma = {nullptr, nullptr, nullptr, 0, 0, nullptr};
+        render_tile<0, kMlpPrec, kFeatF16, kLevels>(table[w.scene], w.cam, tile - w.cam.tile_start, tile, tp, ma, lds,
+                                                    lane);
+        __syncthreads();
+        i = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl(nx, 0, 64));
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(ctl->done, 1u) == gridDim.x - 1) {
+#pragma unroll
+            for (int k = 0; k < kXcds; ++k) atomicExch(ctl->next + k * kCtlStride, 0u);
+            atomicExch(ctl->done, 0u);
         }
     }
 }
@@ -1258,6 +1356,28 @@ const void *render_kernel(const RenderBatch &rb) {
 }
 
 dim3 render_grid(const RenderBatch &rb) { return dim3((unsigned)rb.total_tiles); }
+
+template <bool kFeatF16, bool kLevels>
+const void *served_kernel_mlp(int mlp_prec) {
+    return mlp_prec == 0 ? (const void *)k_render_served<0, kFeatF16, kLevels>
+         : mlp_prec == 1 ? (const void *)k_render_served<1, kFeatF16, kLevels>
+                         : (const void *)k_render_served<2, kFeatF16, kLevels>;
+}
+
+const void *served_kernel(int mlp_prec, int feat_prec, int skip_mode) {
+    if (feat_prec) return skip_mode ? served_kernel_mlp<true, true>(mlp_prec) : served_kernel_mlp<true, false>(mlp_prec);
+    return skip_mode ? served_kernel_mlp<false, true>(mlp_prec) : served_kernel_mlp<false, false>(mlp_prec);
+}
+
+hipError_t launch_render_served(const DevScene *table, const ServeLaunch *launch, ServeCtl *ctl, int mlp_prec,
+                                int feat_prec, int skip_mode, int grid, hipStream_t stream) {
+    if (grid < kXcds || grid % kXcds != 0) return hipErrorInvalidValue;
+    ConstScene *t = (ConstScene *)table;
+    ConstLaunch *l = (ConstLaunch *)launch;
+    void *args[] = {&t, &l, &ctl};
+    return hipLaunchKernel(served_kernel(mlp_prec, feat_prec, skip_mode), dim3((unsigned)grid), dim3(kRenderBlock),
+                           args, 0, stream);
+}
 
 hipError_t launch_render(const DevScene &sc, const RenderBatch &rb, hipStream_t stream) {
     if (rb.total_tiles <= 0) return hipSuccess;

@@ -295,8 +295,10 @@ class merf_server_config(C.Structure):
 
 class merf_server_stats(C.Structure):
     _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("launches", C.c_uint64),
-                ("graph_launches", C.c_uint64), ("evictions", C.c_uint64), ("resident_bytes", C.c_size_t),
-                ("resident_scenes", C.c_int32), ("max_inflight", C.c_int32)]
+                ("graph_launches", C.c_uint64), ("mixed_launches", C.c_uint64), ("evictions", C.c_uint64),
+                ("admissions", C.c_uint64), ("admission_us", C.c_uint64),
+                ("resident_bytes", C.c_size_t), ("resident_scenes", C.c_int32), ("registered", C.c_int32),
+                ("max_inflight", C.c_int32), ("pad", C.c_int32)]
 
 
 SERVE_EXPORTS = ["merf_server_create", "merf_server_destroy", "merf_server_add_scene", "merf_server_remove_scene",

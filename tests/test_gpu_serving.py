@@ -1,7 +1,8 @@
 """GPU tests of the serving runtime (include/merf_serve.h): continuous
-batching of uneven requests over several resident scenes must give every
-request exactly the image merf_render gives it alone; admission follows the
-device-memory budget."""
+batching of uneven requests over several scenes, fused into persistent
+launches across scenes, must give every request exactly the image
+merf_render gives it alone; scenes are admitted by the device-memory budget,
+evicted least recently used first and re-admitted on demand."""
 import threading
 import time
 
@@ -72,19 +73,27 @@ def test_mix_equals_alone(torch, merf, scenes, use_graphs):
         outs = [torch.full((int(w) * int(h), 4), float("nan"), device="cuda") for w, h in cams.size]
         torch.cuda.synchronize()
         tickets = []
+        steps = [0.0 if i % 4 else 1.0 / 48 for i in range(len(cams))]   # default step 4/R, or a coarser one
         for i in range(len(cams)):
-            p = merf.render_params(mlp_prec=prec[i])
+            p = merf.render_params(mlp_prec=prec[i], step=steps[i])
             tickets.append(srv.submit(ids[scene_of[i]], arr, i, outs[i].data_ptr(), p))
         lats = [srv.wait(t)[0] for t in tickets]
         st = srv.stats()
-        say(f"  launches {st['launches']} (graph {st['graph_launches']}), max in flight {st['max_inflight']}, "
-            f"latency p50 {np.percentile(lats, 50):.3f} ms")
+        say(f"  launches {st['launches']} (graph {st['graph_launches']}, mixed-scene {st['mixed_launches']}), "
+            f"max in flight {st['max_inflight']}, latency p50 {np.percentile(lats, 50):.3f} ms")
         assert st["completed"] == len(cams)
         assert st["launches"] < len(cams)            # requests were fused
+        assert st["mixed_launches"] >= 1             # ... across scenes
         if use_graphs:
             assert st["graph_launches"] == st["launches"]
         for i in range(len(cams)):
-            alone = render_alone(torch, merf, scenes[scene_of[i]], cams, i, prec[i])
+            r = merf.Renderer(scenes[scene_of[i]])
+            try:
+                alone = r.render(cams.subset(i), mlp_prec=prec[i], step=steps[i])
+                torch.cuda.synchronize()
+                alone = alone.cpu().numpy()
+            finally:
+                r.close()
             assert np.array_equal(outs[i].cpu().numpy(), alone), i
     finally:
         srv.close()
@@ -149,33 +158,102 @@ def test_arrivals_while_running_are_admitted(torch, merf, scenes):
 def test_admission_by_budget_and_eviction(torch, merf, scenes):
     say("serving: scene admission under an HBM budget")
     probe = merf.Server(slots=1)
-    sid = probe.add_scene(scenes[0])
+    probe.add_scene(scenes[0])
     one = probe.stats()["resident_bytes"]
     probe.close()
     budget = 2 * one + one // 2                        # room for two scenes
+    big = synth.preset_scene("tiny", seed=9)
+    with pytest.raises(merf.MerfError) as e:           # a scene alone above the budget
+        merf.Server(slots=1, hbm_budget=one // 2).add_scene(big)
+    assert e.value.code == merf.MERF_E_OOM
+    cams = synth.random_cameras(1, seed=3, sizes=[(48, 40)], inside=2.5)
+    arr = merf.camera_array(cams)
+    # without eviction: the third scene registers but stays absent; its
+    # request waits until a removal frees memory
     srv = merf.Server(slots=2, hbm_budget=budget)
     try:
-        a, b = srv.add_scene(scenes[0]), srv.add_scene(scenes[1])
-        with pytest.raises(merf.MerfError) as e:
-            srv.add_scene(scenes[2])
-        assert e.value.code == merf.MERF_E_OOM
-        assert srv.stats()["resident_scenes"] == 2
+        a, b, c = [srv.add_scene(s) for s in scenes]
+        st = srv.stats()
+        assert st["registered"] == 3 and st["resident_scenes"] == 2 and st["resident_bytes"] <= budget
+        out = torch.full((48 * 40, 4), float("nan"), device="cuda")
+        torch.cuda.synchronize()
+        t = srv.submit(c, arr, 0, out.data_ptr(), merf.render_params())
+        time.sleep(0.2)
+        assert not srv.poll(t)                          # no memory for scene c yet
         srv.remove_scene(a)
-        c = srv.add_scene(scenes[2])
-        assert srv.stats()["resident_bytes"] <= budget
+        srv.wait(t)
+        st = srv.stats()
+        assert st["resident_scenes"] == 2 and st["admissions"] == 3 and st["evictions"] == 0
+        alone = render_alone(torch, merf, scenes[2], cams, 0, "f32")
+        assert np.array_equal(out.cpu().numpy(), alone)
     finally:
         srv.close()
-    srv = merf.Server(slots=2, hbm_budget=budget, evict_idle=True)
+    # with eviction: requests cycling over three scenes that do not fit
+    # together; scenes are evicted least recently used first and re-admitted
+    srv = merf.Server(slots=2, max_batch=4, hbm_budget=budget, evict_idle=True)
     try:
-        ids = [srv.add_scene(s) for s in scenes]         # the third evicts the least recently used
+        ids = [srv.add_scene(s) for s in scenes]
+        assert srv.stats()["resident_scenes"] == 2
+        n = 30
+        order = [i % 3 for i in range(n)]
+        cams = synth.random_cameras(n, seed=5, sizes=[(40, 24), (64, 64), (17, 9)] * 10, inside=2.5)
+        arr = merf.camera_array(cams)
+        outs = [torch.full((int(w) * int(h), 4), float("nan"), device="cuda") for w, h in cams.size]
+        torch.cuda.synchronize()
+        ts = [srv.submit(ids[order[i]], arr, i, outs[i].data_ptr(), merf.render_params()) for i in range(n)]
+        for t in ts:
+            srv.wait(t)
         st = srv.stats()
-        assert st["evictions"] == 1 and st["resident_scenes"] == 2
-        cams = synth.tiny_camera(w=32, h=32)
-        out = torch.empty((32 * 32, 4), device="cuda")
-        with pytest.raises(merf.MerfError):
-            srv.submit(ids[0], merf.camera_array(cams), 0, out.data_ptr(), merf.render_params())
-        t = srv.submit(ids[2], merf.camera_array(cams), 0, out.data_ptr(), merf.render_params())
-        srv.wait(t)
+        say(f"  launches {st['launches']}, admissions {st['admissions']}, evictions {st['evictions']}")
+        assert st["completed"] == n and st["evictions"] >= 1 and st["admissions"] == 2 + st["evictions"]
+        assert st["resident_bytes"] <= budget and st["resident_scenes"] <= 2
+        for i in range(n):
+            alone = render_alone(torch, merf, scenes[order[i]], cams, i, "f32")
+            assert np.array_equal(outs[i].cpu().numpy(), alone), i
+    finally:
+        srv.close()
+
+
+def test_admission_while_serving_from_threads(torch, merf, scenes):
+    """Two client threads keep requesting four scenes, of which two fit: the
+    loader must drain and evict scenes that are in use, and every request
+    still gets its image."""
+    say("serving: admission by memory under load from two threads")
+    probe = merf.Server(slots=1)
+    probe.add_scene(scenes[0])
+    one = probe.stats()["resident_bytes"]
+    probe.close()
+    four = scenes + [synth.preset_scene("tiny", seed=4)]
+    srv = merf.Server(slots=3, max_batch=6, hbm_budget=2 * one + one // 2, evict_idle=True)
+    try:
+        ids = [srv.add_scene(s) for s in four]
+        n = 48
+        rng = np.random.default_rng(17)
+        which = rng.integers(0, 4, n)
+        cams = synth.random_cameras(n, seed=19, sizes=[(32, 32), (56, 24)] * (n // 2), inside=2.5)
+        arr = merf.camera_array(cams)
+        outs = [torch.full((int(w) * int(h), 4), float("nan"), device="cuda") for w, h in cams.size]
+        torch.cuda.synchronize()
+        tickets = [None] * n
+
+        def client(k):
+            for i in range(k, n, 2):
+                tickets[i] = srv.submit(ids[which[i]], arr, i, outs[i].data_ptr(), merf.render_params())
+                time.sleep(0.0005)
+
+        ths = [threading.Thread(target=client, args=(k,)) for k in (0, 1)]
+        for th in ths:
+            th.start()
+        for th in ths:
+            th.join()
+        srv.drain()
+        st = srv.stats()
+        say(f"  launches {st['launches']} (mixed-scene {st['mixed_launches']}), admissions {st['admissions']}, "
+            f"evictions {st['evictions']}")
+        assert st["completed"] == n and st["evictions"] >= 1
+        for i in range(n):
+            alone = render_alone(torch, merf, four[which[i]], cams, i, "f32")
+            assert np.array_equal(outs[i].cpu().numpy(), alone), i
     finally:
         srv.close()
 
