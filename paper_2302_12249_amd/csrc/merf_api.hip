@@ -564,6 +564,8 @@ int upload_impl(const merf_scene_desc *desc, merf_scene_t *out, bool ordered, hi
     ds.d_off = -ds.nsrc * ds.m_density;
     ds.f_scale = eq8_scale(ds.m_feature);
     ds.f_off = -ds.nsrc * ds.m_feature;
+    ds.d_scale24 = ds.d_scale * 16777216.0f;     // exact: a power of two
+    ds.f_scale24 = ds.f_scale * 16777216.0f;
     ds.grid_w = L > 0 ? 1.0f : 0.0f;
     ds.planes_w = R > 0 ? 1.0f : 0.0f;
     ds.dist_scale = (float)ds.dist_res * 0.25f;

@@ -79,6 +79,7 @@ struct DevScene {
     float g_scale, g_off, g_max;                 // grid voxel coordinate, the same with L
     float d_scale, d_off;                        // density: 2 m_d / 255 and -nsrc m_d
     float f_scale, f_off;                        // appearance: 2 m_f / 255 and -nsrc m_f
+    float d_scale24, f_scale24;                  // d_scale, f_scale times 2^24 (codes read as b * 2^-24)
     float dist_scale, dist_off;                  // empty-space cell: fma(p, r_f/4, r_f/2)
 };
 

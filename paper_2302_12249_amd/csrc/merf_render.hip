@@ -68,6 +68,22 @@ __device__ __forceinline__ float deq_f16(uint32_t b, float a, float m) {
 
 __device__ __forceinline__ uint32_t byte_of(uint32_t w, int i) { return (w >> (8 * i)) & 0xffu; }
 
+// Two codes as the float16 subnormals b * 2^-24, which are exact: mixed-
+// precision FMAs (v_fma_mix_f32) then take them as operands directly, so an
+// interpolation term costs one instruction instead of a convert and an FMA.
+// The sums come out scaled by 2^-24 exactly (a power of two, far from the
+// float32 range limits), which the Eq. 8 scale absorbs.
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ f16x2 as_f16x2(uint32_t w) { return __builtin_bit_cast(f16x2, w); }
+// bytes 0 and 2 of w
+__device__ __forceinline__ f16x2 codes02(uint32_t w) { return as_f16x2(w & 0x00ff00ffu); }
+// bytes 1 and 3 of w
+__device__ __forceinline__ f16x2 codes13(uint32_t w) { return as_f16x2(__builtin_amdgcn_perm(0u, w, 0x0c030c01u)); }
+// byte 0 of a and byte 0 of b
+__device__ __forceinline__ f16x2 codes0_0(uint32_t a, uint32_t b) {
+    return as_f16x2(__builtin_amdgcn_perm(b, a, 0x0c040c00u));
+}
+
 // Hardware reciprocal (v_rcp_f32, 1 ulp); rcp(+-0) = +-inf.
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
@@ -366,9 +382,14 @@ __device__ __forceinline__ SampleResult eval_sample(const S &sc, float3 p, float
 #pragma unroll
         for (int i = 0; i < 20; ++i) s0 = fmaf(w[i], deq_f16(byte_of(lo[i], 0), sc.d_scale, md), s0);
     } else {
+        // texel pairs: the density codes of texels 2k and 2k + 1 in one word
 #pragma unroll
-        for (int i = 0; i < 20; ++i) s0 = fmaf(w[i], (float)byte_of(lo[i], 0), s0);
-        s0 = fmaf(s0, sc.d_scale, sc.d_off);
+        for (int k = 0; k < 10; ++k) {
+            const f16x2 c = codes0_0(lo[2 * k], lo[2 * k + 1]);
+            s0 = fmaf(w[2 * k], (float)c.x, s0);
+            s0 = fmaf(w[2 * k + 1], (float)c.y, s0);
+        }
+        s0 = fmaf(s0, sc.d_scale24, sc.d_off);
     }
     SampleResult r;
     float tau = __expf(s0);                       // Eq. 6
@@ -389,13 +410,18 @@ __device__ __forceinline__ SampleResult eval_sample(const S &sc, float3 p, float
         } else {
 #pragma unroll
             for (int i = 0; i < 20; ++i) {
-#pragma unroll
-                for (int c = 1; c < 4; ++c) sa[c - 1] = fmaf(w[i], (float)byte_of(lo[i], c), sa[c - 1]);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) sa[3 + c] = fmaf(w[i], (float)byte_of(hi[i], c), sa[3 + c]);
+                const f16x2 l02 = codes02(lo[i]), l13 = codes13(lo[i]);
+                const f16x2 h02 = codes02(hi[i]), h13 = codes13(hi[i]);
+                sa[0] = fmaf(w[i], (float)l13.x, sa[0]);
+                sa[1] = fmaf(w[i], (float)l02.y, sa[1]);
+                sa[2] = fmaf(w[i], (float)l13.y, sa[2]);
+                sa[3] = fmaf(w[i], (float)h02.x, sa[3]);
+                sa[4] = fmaf(w[i], (float)h13.x, sa[4]);
+                sa[5] = fmaf(w[i], (float)h02.y, sa[5]);
+                sa[6] = fmaf(w[i], (float)h13.y, sa[6]);
             }
 #pragma unroll
-            for (int c = 0; c < 7; ++c) sa[c] = fmaf(sa[c], af, sc.f_off);
+            for (int c = 0; c < 7; ++c) sa[c] = fmaf(sa[c], sc.f_scale24, sc.f_off);
         }
 #pragma unroll
         for (int c = 0; c < 7; ++c) r.sg[c] = sigmoid(sa[c]);

@@ -329,9 +329,9 @@ def _serve_lib():
 
 MEASURE_EXPORTS = ["merf_gather_slots", "merf_record_gathers", "merf_render_phases", "merf_render_timed",
                    "merf_replay_gathers"]
+# slots of the phase profile, in the kernel's order (enum PhaseSlot)
 PHASE_FIELDS = ["setup_cycles", "march_cycles", "open_cycles", "shade_cycles", "composite_cycles", "mlp_cycles",
-                "total_cycles", "waves", "march_passes", "open_passes", "open_lanes", "shade_passes",
-                "shade_lanes", "rounds"]
+                "waves", "march_passes", "open_passes", "open_lanes", "shade_passes", "shade_lanes", "rounds"]
 
 
 def _measure_lib():

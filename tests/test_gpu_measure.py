@@ -1,6 +1,7 @@
-"""GPU tests of the gather record / replay measurement (include/merf_measure.h):
-recording renders the same image as merf_render, records one entry per
-evaluated sample with in-range offsets, and the replay re-issues them."""
+"""GPU tests of the measurement entry points (include/merf_measure.h): the
+gather record renders the same image as merf_render, records one entry per
+evaluated sample with in-range offsets, and the replay re-issues them; the
+phase profile renders the same image and fills its slots consistently."""
 import numpy as np
 import pytest
 
@@ -81,5 +82,32 @@ def test_record_full_view_heavy_first_order(torch, merf):
         torch.cuda.synchronize()
         assert np.array_equal(rec2.order.cpu().numpy(), np.arange(tiles))
         assert torch.equal(rec2.count, rec.count)
+    finally:
+        r.close()
+
+
+def test_phase_profile_fields(torch, merf, tiny_scene):
+    """merf_render_phases: same image as merf_render; one wave per tile; the
+    loop counters in their slots agree with the statistics counters."""
+    print("phase profile, tiny view", flush=True)
+    cams = synth.tiny_camera(w=100, h=60)          # 13 x 8 tiles
+    r = merf.Renderer(tiny_scene)
+    try:
+        plain = r.render(cams)
+        out = torch.empty_like(plain)
+        ph = merf.render_phases(r.handle, cams, out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, plain)
+        st = ph["stats"]
+        assert ph["waves"] == 13 * 8
+        assert st["rays"] == 100 * 60
+        # every evaluated sample is shaded once; samples parked past a ray's
+        # termination are shaded and dropped
+        assert ph["shade_lanes"] >= st["evaluated"]
+        assert ph["shade_lanes"] <= 64 * ph["shade_passes"]
+        assert ph["rounds"] >= ph["shade_passes"] >= 1
+        assert ph["march_passes"] >= ph["open_passes"]
+        for k in ("setup_cycles", "march_cycles", "shade_cycles", "composite_cycles", "mlp_cycles"):
+            assert ph[k] > 0, k
     finally:
         r.close()
