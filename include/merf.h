@@ -17,7 +17,8 @@
  * All functions return 0 (MERF_OK) or a negative error code; a message for
  * the calling thread's last error is available from merf_last_error().
  * Every error path releases whatever the failing call had allocated.
- * Host pointers are read during the call only; the caller keeps ownership.
+ * Pointers passed in are read during the call only; the caller keeps
+ * ownership.
  */
 #ifndef MERF_H
 #define MERF_H
@@ -41,7 +42,7 @@ extern "C" {
 typedef struct merf_scene *merf_scene_t;
 
 /*
- * Baked scene, host memory (Sec. 4.1 representation, Sec. 5.3 baking, Sec. 6
+ * Baked scene (Sec. 4.1 representation, Sec. 5.3 baking, Sec. 6
  * occupancy hierarchy).  Channel order of every texel: [density, diffuse r,
  * g, b, feature 0..3] (C = 4 + K with K = 4).
  *
@@ -68,6 +69,11 @@ typedef struct merf_scene *merf_scene_t;
  *  mlp_hidden      deferred MLP shape; must be 34 and 16 (App. B: 3 layers,
  *                  16 hidden units, 4 direction frequencies).
  *  mlp_params      float32 W0[in][h], b0[h], W1[h][h], b1[h], W2[h][3], b2[3].
+ *
+ * block_index must be host memory (the upload reads it to lay the bricks
+ * out).  blocks, planes, occ[l] and mlp_params may be host memory or device
+ * memory of the current device: an occupancy pyramid built on the device by
+ * merf_occupancy_pyramid is uploaded without a trip through the host.
  */
 typedef struct {
     uint32_t struct_size;                 /* = sizeof(merf_scene_desc) */
@@ -137,7 +143,8 @@ typedef struct {
 
 /*
  * Copy a baked scene into device memory and return its handle.
- * desc and every array it points to are host memory, read during the call.
+ * desc and the arrays it points to (host or device memory, see
+ * merf_scene_desc) are read during the call.
  * The library re-lays the data out for the GPU (sparse grid blocks padded
  * with a one-voxel apron so a trilinear footprint never spans two blocks)
  * and derives the empty-space distance grid of skip_mode 0 (one byte per

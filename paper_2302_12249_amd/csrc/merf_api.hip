@@ -497,8 +497,10 @@ int upload_impl(const merf_scene_desc *desc, merf_scene_t *out, bool ordered, hi
     }
     for (const Copy &c : copies) {
         if (c.n == 0) continue;
-        e = ordered ? hipMemcpyAsync(c.dst, c.src, c.n, hipMemcpyHostToDevice, stream)
-                    : hipMemcpy(c.dst, c.src, c.n, hipMemcpyHostToDevice);
+        // hipMemcpyDefault: blocks, planes, occupancy levels and MLP may be
+        // host or device memory (e.g. a pyramid built by merf_occupancy_pyramid)
+        e = ordered ? hipMemcpyAsync(c.dst, c.src, c.n, hipMemcpyDefault, stream)
+                    : hipMemcpy(c.dst, c.src, c.n, hipMemcpyDefault);
         if (e != hipSuccess) break;
     }
     if (e == hipSuccess && R == 0) e = hipMemsetAsync(dev(o_planes), 0, (size_t)3 * 2 * 2 * kChannels, stream);

@@ -497,9 +497,17 @@ void loader_main(merf_server *S) {
     }
 }
 
+void free_host(SceneEntry &e) {
+    if (!e.host) return;
+    if (e.pinned) (void)hipHostFree(e.host);
+    else std::free(e.host);
+    e.host = nullptr;
+}
+
 // The server's host copy of a scene descriptor's arrays, in one buffer:
 // pinned memory when it can be had (uploads are then plain DMA), else
-// pageable.  Returns false if no memory could be had.
+// pageable.  The arrays may be host or device memory, except block_index
+// (host).  Returns false if no memory could be had or a copy failed.
 bool copy_scene(const merf_scene_desc *d, SceneEntry &e) {
     const size_t nbl = (size_t)(d->grid_res / 8);
     const size_t n_idx = nbl * nbl * nbl * sizeof(int32_t);
@@ -519,9 +527,10 @@ bool copy_scene(const merf_scene_desc *d, SceneEntry &e) {
         if (!e.host) return false;
     }
     uint8_t *at = static_cast<uint8_t *>(e.host);
-    auto put = [&](const void *src, size_t n) -> uint8_t * {
+    bool ok = true;
+    auto put = [&](const void *src, size_t n) -> uint8_t * {   // src: host or device memory
         uint8_t *dst = at;
-        if (n) std::memcpy(dst, src, n);
+        if (n) ok = ok && hipMemcpy(dst, src, n, hipMemcpyDefault) == hipSuccess;
         at += up(n);
         return dst;
     };
@@ -532,14 +541,11 @@ bool copy_scene(const merf_scene_desc *d, SceneEntry &e) {
     for (int l = 0; l < MERF_MAX_OCC_LEVELS; ++l) e.desc.occ[l] = l < d->occ_levels ? put(d->occ[l], n_occ[l]) : nullptr;
     e.desc.mlp_params = reinterpret_cast<const float *>(put(d->mlp_params, n_mlp));
     e.res = std::max(std::max(d->grid_res, d->plane_res), 1);
-    return true;
-}
-
-void free_host(SceneEntry &e) {
-    if (!e.host) return;
-    if (e.pinned) (void)hipHostFree(e.host);
-    else std::free(e.host);
-    e.host = nullptr;
+    if (!ok) {
+        (void)hipGetLastError();
+        free_host(e);
+    }
+    return ok;
 }
 
 void destroy_slots(merf_server *S) {
@@ -640,7 +646,7 @@ int merf_server_add_scene(merf_server_t S, const merf_scene_desc *desc, int32_t 
     }
     if (need > S->budget) return fail(MERF_E_OOM, "scene needs %zu device bytes, the budget is %zu", need, S->budget);
     SceneEntry fresh;
-    if (!copy_scene(desc, fresh)) return fail(MERF_E_OOM, "no host memory for the server's copy of the scene");
+    if (!copy_scene(desc, fresh)) return fail(MERF_E_OOM, "no host memory for (or no copy into) the server's copy of the scene");
     fresh.need = need;
     SceneEntry *se = nullptr;
     int32_t id = 0;

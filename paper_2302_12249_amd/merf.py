@@ -123,23 +123,29 @@ def scene_desc(scene):
         keep.append(a)
         return a
 
-    bi = arr(scene.block_index, np.int32)
-    blocks = arr(scene.blocks, np.uint8)
-    planes = arr(scene.planes, np.uint8)
-    mlp = arr(scene.mlp, np.float32)
+    def ptr(a, dt):
+        """Address of a numpy array, or of a contiguous cuda tensor of the
+        same element size (blocks, planes, occupancy levels and MLP may be
+        device memory)."""
+        if hasattr(a, "data_ptr") and getattr(a, "is_cuda", False):
+            assert a.is_contiguous() and a.element_size() == np.dtype(dt).itemsize
+            keep.append(a)
+            return a.data_ptr()
+        return _ptr(arr(a, dt))
+
+    bi = arr(scene.block_index, np.int32)               # read on the host by the upload
     d.grid_res, d.block_size, d.plane_res, d.channels = scene.L, scene.B, scene.R, scene.C
-    d.num_blocks = int(blocks.shape[0])
+    d.num_blocks = int(scene.blocks.shape[0])
     d.block_index = _ptr(bi)
-    d.blocks = _ptr(blocks) if blocks.size else None
-    d.planes = _ptr(planes)
+    d.blocks = ptr(scene.blocks, np.uint8) if d.num_blocks else None
+    d.planes = ptr(scene.planes, np.uint8)
     d.occ_levels = len(scene.occ)
     for i, (r, o) in enumerate(scene.occ):
-        oo = arr(o, np.uint8)
         d.occ_res[i] = int(r)
-        d.occ[i] = _ptr(oo)
+        d.occ[i] = ptr(o, np.uint8)
     d.m_density, d.m_feature = float(scene.m_density), float(scene.m_feature)
     d.mlp_in, d.mlp_hidden = scene.mlp_in, scene.mlp_hidden
-    d.mlp_params = _ptr(mlp)
+    d.mlp_params = ptr(scene.mlp, np.float32)
     return d, keep
 
 

@@ -1,6 +1,6 @@
 """GPU tests of device-side ingest: the occupancy max-pool entry point
-matches a numpy max-pool bit for bit, and the same pyramid drives the
-renderer to the oracle's image."""
+matches a numpy max-pool bit for bit, and the pyramid it builds is uploaded
+from device memory and drives the renderer to the oracle's image."""
 import numpy as np
 import pytest
 
@@ -37,23 +37,48 @@ def test_maxpool_matches_numpy(torch, merf, res, factors):
 
 
 def test_device_pyramid_renders_like_host_pyramid(torch, merf, tiny_scene, tiny_cams):
-    print("tiny scene with a device-built occupancy pyramid", flush=True)
+    """The pyramid built on the device (merf_occupancy_pyramid) is uploaded
+    straight from device memory -- by merf_scene_upload and by the server --
+    and renders the oracle's image."""
+    print("tiny scene with a device-built occupancy pyramid, uploaded from device memory", flush=True)
+    import dataclasses
     fine = tiny_scene.occ[-1][1]
     outs = merf.occupancy_pyramid(torch.from_numpy(np.ascontiguousarray(fine)).cuda(), (2, 1))
     torch.cuda.synchronize()
-    import dataclasses
-    sc = dataclasses.replace(tiny_scene, occ=[(o.shape[0], o.cpu().numpy()) for o in outs])
-    assert all(np.array_equal(a[1], b[1]) for a, b in zip(sc.occ, tiny_scene.occ))
+    assert all(np.array_equal(o.cpu().numpy(), h[1]) for o, h in zip(outs, tiny_scene.occ))
+    # levels, planes and blocks as device tensors (block_index stays on the host)
+    sc = dataclasses.replace(tiny_scene, occ=[(o.shape[0], o) for o in outs],
+                             planes=torch.from_numpy(np.ascontiguousarray(tiny_scene.planes)).cuda(),
+                             blocks=torch.from_numpy(np.ascontiguousarray(tiny_scene.blocks)).cuda())
     r = merf.Renderer(sc)
     try:
         gpu = r.render(tiny_cams)
         torch.cuda.synchronize()
-        gpu = gpu.cpu().numpy().astype(np.float64)
+        gpu = gpu.cpu().numpy()
     finally:
         r.close()
     ref, st = oracle.render(tiny_scene, tiny_cams)
     ok = st["fragile"] == 0
-    assert np.abs(gpu - ref)[ok].max() <= 2.0 / 255.0
+    assert np.abs(gpu.astype(np.float64) - ref)[ok].max() <= 2.0 / 255.0
+    assert np.abs(gpu.astype(np.float64) - ref).mean() <= 1e-3
+    # the same image as the host-built pyramid, bit for bit
+    r = merf.Renderer(tiny_scene)
+    try:
+        host = r.render(tiny_cams)
+        torch.cuda.synchronize()
+        assert np.array_equal(host.cpu().numpy(), gpu)
+    finally:
+        r.close()
+    # the server registers the scene from the same device arrays
+    srv = merf.Server(slots=1)
+    try:
+        sid = srv.add_scene(sc)
+        out = torch.full((tiny_cams.num_pixels(), 4), float("nan"), device="cuda")
+        torch.cuda.synchronize()
+        srv.wait(srv.submit(sid, merf.camera_array(tiny_cams), 0, out.data_ptr(), merf.render_params()))
+        assert np.array_equal(out.cpu().numpy(), gpu)
+    finally:
+        srv.close()
 
 
 def chebyshev_brute(levels):
