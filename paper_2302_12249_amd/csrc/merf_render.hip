@@ -57,14 +57,6 @@ __device__ __forceinline__ float deq_f32(uint32_t b, float m2, float m255) {
     return fmaf(r, kRcp255, q);
 }
 
-// Eq. 8 to float16 with a = RN32(2m/255) (the scale the upload computes):
-// RN16(RN32(b a - m)) equals the correctly rounded float16 of the exact
-// 2mb/255 - m for every code and m in {7, 14} (checked exhaustively on the
-// host, and bit for bit on the device through merf_dequantize); returned
-// widened to float.
-__device__ __forceinline__ float deq_f16(uint32_t b, float a, float m) {
-    return (float)(_Float16)fmaf((float)b, a, -m);
-}
 
 __device__ __forceinline__ uint32_t byte_of(uint32_t w, int i) { return (w >> (8 * i)) & 0xffu; }
 
@@ -82,6 +74,18 @@ __device__ __forceinline__ f16x2 codes13(uint32_t w) { return as_f16x2(__builtin
 // byte 0 of a and byte 0 of b
 __device__ __forceinline__ f16x2 codes0_0(uint32_t a, uint32_t b) {
     return as_f16x2(__builtin_amdgcn_perm(b, a, 0x0c040c00u));
+}
+
+// Eq. 8 to float16 of a code given as the subnormal b 2^-24, with
+// a24 = 2^24 RN32(2m/255) (the scale the upload computes, times 2^24): the
+// product is b RN32(2m/255) exactly, so this is RN16(RN32(b a - m)), which
+// equals the correctly rounded float16 of the exact 2mb/255 - m for every
+// code and m in {7, 14} (checked exhaustively on the host, and bit for bit on
+// the device through merf_dequantize, which runs this routine).  Returned
+// widened to float; the compiler fuses the FMA and the rounding to float16
+// into one mixed-precision instruction.
+__device__ __forceinline__ float deq_f16(_Float16 code, float a24, float m) {
+    return (float)(_Float16)fmaf((float)code, a24, -m);
 }
 
 // Hardware reciprocal (v_rcp_f32, 1 ulp); rcp(+-0) = +-inf.
@@ -380,7 +384,11 @@ __device__ __forceinline__ SampleResult eval_sample(const S &sc, float3 p, float
 #pragma unroll
         for (int i = 0; i < 20; ++i) w[i] *= i < 8 ? sc.grid_w : sc.planes_w;
 #pragma unroll
-        for (int i = 0; i < 20; ++i) s0 = fmaf(w[i], deq_f16(byte_of(lo[i], 0), sc.d_scale, md), s0);
+        for (int k = 0; k < 10; ++k) {
+            const f16x2 c = codes0_0(lo[2 * k], lo[2 * k + 1]);
+            s0 = fmaf(w[2 * k], deq_f16(c.x, sc.d_scale24, md), s0);
+            s0 = fmaf(w[2 * k + 1], deq_f16(c.y, sc.d_scale24, md), s0);
+        }
     } else {
         // texel pairs: the density codes of texels 2k and 2k + 1 in one word
 #pragma unroll
@@ -398,14 +406,19 @@ __device__ __forceinline__ SampleResult eval_sample(const S &sc, float3 p, float
         float sa[7];
 #pragma unroll
         for (int c = 0; c < 7; ++c) sa[c] = 0.0f;
-        const float af = sc.f_scale;
         if constexpr (kFeatF16) {
+            const float af = sc.f_scale24;
 #pragma unroll
             for (int i = 0; i < 20; ++i) {
-#pragma unroll
-                for (int c = 1; c < 4; ++c) sa[c - 1] = fmaf(w[i], deq_f16(byte_of(lo[i], c), af, mf), sa[c - 1]);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) sa[3 + c] = fmaf(w[i], deq_f16(byte_of(hi[i], c), af, mf), sa[3 + c]);
+                const f16x2 l02 = codes02(lo[i]), l13 = codes13(lo[i]);
+                const f16x2 h02 = codes02(hi[i]), h13 = codes13(hi[i]);
+                sa[0] = fmaf(w[i], deq_f16(l13.x, af, mf), sa[0]);
+                sa[1] = fmaf(w[i], deq_f16(l02.y, af, mf), sa[1]);
+                sa[2] = fmaf(w[i], deq_f16(l13.y, af, mf), sa[2]);
+                sa[3] = fmaf(w[i], deq_f16(h02.x, af, mf), sa[3]);
+                sa[4] = fmaf(w[i], deq_f16(h13.x, af, mf), sa[4]);
+                sa[5] = fmaf(w[i], deq_f16(h02.y, af, mf), sa[5]);
+                sa[6] = fmaf(w[i], deq_f16(h13.y, af, mf), sa[6]);
             }
         } else {
 #pragma unroll
@@ -1346,7 +1359,8 @@ __global__ void k_dequant(const uint8_t *__restrict__ codes, int64_t n, float m,
     const float m2 = 2.0f * m, m255 = 255.0f * m;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         if (prec == 1) {
-            reinterpret_cast<__half *>(out)[i] = __float2half_rn(deq_f16(codes[i], a, m));
+            const _Float16 code = as_f16x2((uint32_t)codes[i]).x;     // the subnormal b 2^-24
+            reinterpret_cast<__half *>(out)[i] = __float2half_rn(deq_f16(code, a * 16777216.0f, m));
         } else {
             const float v = deq_f32(codes[i], m2, m255);
             if (prec == 0) reinterpret_cast<float *>(out)[i] = v;
