@@ -180,11 +180,14 @@ __device__ __forceinline__ int region_at(float3 o, float3 d, float t) {
     return region_of(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
 }
 
+// 24-bit multiply (v_mul_u32_u24, full rate; a 32-bit integer multiply is
+// quarter rate): both factors below 2^24, the low 32 bits of the product.
+__device__ __forceinline__ uint32_t mul24(uint32_t a, uint32_t b) { return __umul24(a, b); }
+
 // Byte offset of cell (x, y, z) of an r^3 z-major grid; every factor is
-// below 2^24 (r <= 1024), so the products are 24-bit multiplies.
+// below 2^24 (r <= 1024).
 __device__ __forceinline__ uint32_t cell_offset(int x, int y, int z, int r) {
-    const uint32_t m = 0xffffffu, ur = (uint32_t)r & m;
-    return (((((uint32_t)z & m) * ur + (uint32_t)y) & m) * ur) + (uint32_t)x;
+    return mul24((uint32_t)z, mul24((uint32_t)r, (uint32_t)r)) + mul24((uint32_t)y, (uint32_t)r) + (uint32_t)x;
 }
 
 // Number of lanes below this one whose bit is set in the wave mask m.
@@ -277,9 +280,11 @@ __device__ __forceinline__ Footprint footprint(const S &sc, float3 p) {
     f.ex = hx - (float)jx; f.ey = hy - (float)jy; f.ez = hz - (float)jz;
     const uint32_t row = (uint32_t)sc.R * kChannels, plane = (uint32_t)sc.R * row;
     f.prow = row;
-    f.op[0] = (uint32_t)jz * row + (uint32_t)jy * kChannels;
-    f.op[1] = plane + (uint32_t)jz * row + (uint32_t)jx * kChannels;
-    f.op[2] = 2u * plane + (uint32_t)jy * row + (uint32_t)jx * kChannels;
+    // (R <= 8192: texel indices and the row of 8 R bytes are below 2^24, and
+    // every offset below 2^31)
+    f.op[0] = mul24((uint32_t)jz, row) + (uint32_t)jy * kChannels;
+    f.op[1] = plane + mul24((uint32_t)jz, row) + (uint32_t)jx * kChannels;
+    f.op[2] = 2u * plane + mul24((uint32_t)jy, row) + (uint32_t)jx * kChannels;
     // ---- sparse 3D grid, trilinear inside one apron brick
     const float gs = sc.g_scale, gs2 = sc.g_off, gmax = sc.g_max;
     float gx = __builtin_amdgcn_fmed3f(fmaf(p.x, gs, gs2), 0.0f, gmax);
@@ -287,7 +292,8 @@ __device__ __forceinline__ Footprint footprint(const S &sc, float3 p) {
     float gz = __builtin_amdgcn_fmed3f(fmaf(p.z, gs, gs2), 0.0f, gmax);
     int ix = min((int)gx, sc.L - 2), iy = min((int)gy, sc.L - 2), iz = min((int)gz, sc.L - 2);
     f.fx = gx - (float)ix; f.fy = gy - (float)iy; f.fz = gz - (float)iz;
-    f.bi = ((uint32_t)(iz >> 3) * sc.nbl + (uint32_t)(iy >> 3)) * sc.nbl + (uint32_t)(ix >> 3);
+    f.bi = mul24((uint32_t)(iz >> 3), mul24((uint32_t)sc.nbl, (uint32_t)sc.nbl)) +
+           mul24((uint32_t)(iy >> 3), (uint32_t)sc.nbl) + (uint32_t)(ix >> 3);
     f.ol = (uint32_t)((((iz & 7) * kBrick + (iy & 7)) * kBrick + (ix & 7)) * kChannels);
     return f;
 }
@@ -314,7 +320,8 @@ __device__ __forceinline__ Texels gather(const S &sc, const Footprint &f) {
         x.t[2 * pl + 1] = load_pair(sc.planes, f.op[pl] + f.prow);
     }
     constexpr uint32_t sy = kBrick * kChannels, sz = kBrick * kBrick * kChannels;
-    const uint32_t ob = (uint32_t)brick * kBrickBytes + f.ol;
+    // (fewer than 2^31 / kBrickBytes bricks: the upload checks it)
+    const uint32_t ob = mul24((uint32_t)brick, kBrickBytes) + f.ol;
     x.g[0] = load_pair(sc.bricks, ob);
     x.g[1] = load_pair(sc.bricks, ob + sy);
     x.g[2] = load_pair(sc.bricks, ob + sz);
@@ -568,7 +575,8 @@ __device__ __forceinline__ int dist_lookup(const S &sc, const Segment &s, float3
 // uexit: the first whose midpoint lies past the exit, and at least k + 1.
 __device__ __forceinline__ int skip_past(const Segment &s, float uexit, float istep) {
     const float kn = floorf((uexit - kSkipGuard) * istep - 0.5f) + 1.0f;
-    const int knext = kn > (float)s.n ? s.n : (int)fmaxf(kn, 0.0f);
+    // clamped to [0, n] (the float-to-int conversion saturates; NaN gives 0)
+    const int knext = min((int)fmaxf(kn, 0.0f), s.n);
     return max(s.k + 1, knext);
 }
 
