@@ -168,13 +168,21 @@ __device__ __forceinline__ Candidates make_candidates(float3 o, float3 d) {
     return C;
 }
 
-// Smallest candidate strictly greater than t (kInf if none).
-__device__ __forceinline__ float next_candidate(const Candidates &C, float t) {
+// Smallest of n candidates strictly greater than t (kInf if none): each
+// candidate is masked to kInf unless above t, then three-way minima.
+template <int n>
+__device__ __forceinline__ float next_of(const float *c, float t) {
     float m = kInf;
 #pragma unroll
-    for (int i = 0; i < 12; ++i) m = (C.c[i] > t && C.c[i] < m) ? C.c[i] : m;
+    for (int i = 0; i < n; i += 3) {
+        const float a = c[i] > t ? c[i] : kInf;
+        const float b = i + 1 < n && c[i + 1] > t ? c[i + 1] : kInf;
+        const float e = i + 2 < n && c[i + 2] > t ? c[i + 2] : kInf;
+        m = fminf(m, fminf(a, fminf(b, e)));
+    }
     return m;
 }
+__device__ __forceinline__ float next_candidate(const Candidates &C, float t) { return next_of<12>(C.c, t); }
 
 __device__ __forceinline__ int region_at(float3 o, float3 d, float t) {
     return region_of(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
@@ -499,15 +507,21 @@ __device__ __forceinline__ void open_segment(float3 o, float3 d, float ta, int r
     // when |x_a| crosses 1 or another |x_k| meets |x_a| (candidates 2a, 2a+1
     // and the pairs with a).  The others are skipped; the next region is
     // still sampled between consecutive candidates of the full set.
+    // the six relevant candidates: cube {0..5}; axis 0 {0, 1, 6, 7, 8, 9};
+    // axis 1 {2, 3, 6, 7, 10, 11}; axis 2 {4, 5, 8, 9, 10, 11}
     const int ax = (reg - 1) >> 1;
-    const uint32_t relevant = reg == 0 ? 0x03Fu : (ax == 0 ? 0x3C3u : (ax == 1 ? 0xCCCu : 0xF30u));
-    Candidates Cr;
-#pragma unroll
-    for (int i = 0; i < 12; ++i) Cr.c[i] = (relevant >> i) & 1u ? C.c[i] : kInf;
+    const bool in_cube = reg == 0, a0 = !in_cube && ax == 0, a1 = !in_cube && ax == 1;
+    float cr[6];
+    cr[0] = in_cube || a0 ? C.c[0] : (a1 ? C.c[2] : C.c[4]);
+    cr[1] = in_cube || a0 ? C.c[1] : (a1 ? C.c[3] : C.c[5]);
+    cr[2] = in_cube ? C.c[2] : (a0 || a1 ? C.c[6] : C.c[8]);
+    cr[3] = in_cube ? C.c[3] : (a0 || a1 ? C.c[7] : C.c[9]);
+    cr[4] = in_cube ? C.c[4] : (a0 ? C.c[8] : C.c[10]);
+    cr[5] = in_cube ? C.c[5] : (a0 ? C.c[9] : C.c[11]);
     float tb = kInf, cur = ta;
     int reg_next = reg;
     for (int it = 0; it < 13; ++it) {
-        float n1 = next_candidate(Cr, cur);
+        float n1 = next_of<6>(cr, cur);
         if (!(n1 < kInf)) break;
         float n2 = next_candidate(C, n1);
         float tm = n2 < kInf ? 0.5f * (n1 + n2) : 2.0f * n1 + 1.0f;
