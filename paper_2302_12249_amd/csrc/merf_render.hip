@@ -649,11 +649,22 @@ __device__ __forceinline__ void mlp_encode(float *x, const Accum &acc, float3 d)
     x[0] = acc.cd0; x[1] = acc.cd1; x[2] = acc.cd2;
     x[3] = acc.f0; x[4] = acc.f1; x[5] = acc.f2; x[6] = acc.f3;
     x[7] = d.x; x[8] = d.y; x[9] = d.z;
+    // sin and cos of 2^k d, k = 0..3: the hardware sine and cosine at k = 0,
+    // then the double-angle identities sin 2a = 2 sin a cos a and
+    // cos 2a = 1 - 2 sin^2 a (three FP32 operations instead of two quarter-
+    // rate transcendentals per term; the error stays near 1e-5 absolute)
+    float sn[3] = {__sinf(d.x), __sinf(d.y), __sinf(d.z)};
+    float cs[3] = {__cosf(d.x), __cosf(d.y), __cosf(d.z)};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const float sc = (float)(1 << k);
-        x[10 + 3 * k] = __sinf(d.x * sc); x[11 + 3 * k] = __sinf(d.y * sc); x[12 + 3 * k] = __sinf(d.z * sc);
-        x[22 + 3 * k] = __cosf(d.x * sc); x[23 + 3 * k] = __cosf(d.y * sc); x[24 + 3 * k] = __cosf(d.z * sc);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            x[10 + 3 * k + a] = sn[a];
+            x[22 + 3 * k + a] = cs[a];
+            const float s2 = 2.0f * sn[a];
+            cs[a] = fmaf(-s2, sn[a], 1.0f);
+            sn[a] = s2 * x[22 + 3 * k + a];
+        }
     }
 #pragma unroll
     for (int k = kMlpIn; k < 48; ++k) x[k] = 0.0f;
