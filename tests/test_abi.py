@@ -165,6 +165,8 @@ def test_bad_handles():
     p = merf.render_params()
     cams = merf.camera_array(synth.tiny_camera())
     assert lib.merf_render(C.c_void_p(0x1234), cams, 1, C.byref(p), C.c_void_p(16), None) == merf.MERF_E_INVALID
+    assert lib.merf_render_noalloc(C.c_void_p(0x1234), cams, 1, C.byref(p), C.c_void_p(16),
+                                   None) == merf.MERF_E_INVALID
     assert merf.scene_bytes(0x1234) == 0
 
 
