@@ -324,7 +324,9 @@ def serving_leg(n_requests: int, seed: int = 200, budget: int = 1 << 30):
 
 def precision_config(steps: int, scene=None):
     """Precision config: the full-size scene as 16 seeded 1920x1080 orbit views in
-    one batched render call; fp32 / fp16 / bf16 MLP and fp16 features, each
+    one batched render call; fp32 / fp16 / bf16 MLP and both fp16 feature
+    modes (every code dequantised to fp16; appearance interpolated from fp16
+    operands), each
     timed (CUDA events around `steps` calls) and compared with the FP64 oracle
     on every 64th row of every view (PSNR over all sampled pixels, max error
     over the pixels the oracle does not flag as fragile)."""
@@ -349,7 +351,9 @@ def precision_config(steps: int, scene=None):
     ok = st["fragile"] == 0
     res = {}
     for name, mlp, feat in (("f32", "f32", "f32"), ("mlp_f16", "f16", "f32"), ("mlp_bf16", "bf16", "f32"),
-                            ("feat_f16_mlp_f16", "f16", "f16"), ("feat_f16_mlp_bf16", "bf16", "f16")):
+                            ("feat_f16_mlp_f16", "f16", "f16"), ("feat_f16_mlp_bf16", "bf16", "f16"),
+                            ("feat_f16i_mlp_f32", "f32", "f16_interp"), ("feat_f16i_mlp_f16", "f16", "f16_interp"),
+                            ("feat_f16i_mlp_bf16", "bf16", "f16_interp")):
         for _ in range(2):
             r.render(cams, out=out, mlp_prec=mlp, feat_prec=feat)
         torch.cuda.synchronize()
@@ -806,7 +810,9 @@ def main():
         # precision variants of the deferred MLP (fp16 / bf16 inputs on MFMA,
         # fp32 accumulation); compositing and transmittance stay fp32
         for name, mlp, feat in (("mlp_f16", "f16", "f32"), ("mlp_bf16", "bf16", "f32"),
-                                ("feat_f16_mlp_f16", "f16", "f16"), ("feat_f16_mlp_bf16", "bf16", "f16")):
+                                ("feat_f16_mlp_f16", "f16", "f16"), ("feat_f16_mlp_bf16", "bf16", "f16"),
+                                ("feat_f16i_mlp_f32", "f32", "f16_interp"), ("feat_f16i_mlp_f16", "f16", "f16_interp"),
+                                ("feat_f16i_mlp_bf16", "bf16", "f16_interp")):
             img = torch.empty_like(out)
             k_ms, ms = timed_frames(merf, r, cams, img, 20, mlp_prec=mlp, feat_prec=feat)
             prec[name] = {"mlp": mlp, "features": feat, "kernel_ms": k_ms, "frame_gpu_ms": ms,

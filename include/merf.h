@@ -116,7 +116,11 @@ typedef struct {
                                              1: world length of its preimage */
     int32_t mlp_prec;                     /* deferred MLP: 0 = fp32, 1 = fp16, 2 = bf16 */
     int32_t feat_prec;                    /* 0 = codes interpolated in fp32; 1 = every code
-                                             dequantised to float16 first (sums stay fp32) */
+                                             dequantised to float16 first (sums stay fp32);
+                                             2 = appearance interpolated from float16
+                                             operands (weights rounded to float16, codes
+                                             exact) by dot products with fp32 sums, density
+                                             as in 0 (the fast reduced-precision mode) */
     int32_t skip_mode;                    /* empty-space skipping, same image either way:
                                              0 = empty-space grid derived from the occupancy
                                              levels at upload (the largest empty cube ahead

@@ -346,7 +346,7 @@ int check_params(const merf_render_params *p, int res, float *step_out) {
     if (!(p->t_min >= 0.0f && p->t_min < 1.0f)) return fail(MERF_E_INVALID, "t_min %g not in [0, 1)", (double)p->t_min);
     if (p->delta_mode != 0 && p->delta_mode != 1) return fail(MERF_E_INVALID, "delta_mode %d", p->delta_mode);
     if (p->mlp_prec < 0 || p->mlp_prec > 2) return fail(MERF_E_INVALID, "mlp_prec %d not in {0, 1, 2}", p->mlp_prec);
-    if (p->feat_prec != 0 && p->feat_prec != 1) return fail(MERF_E_INVALID, "feat_prec %d not in {0, 1}", p->feat_prec);
+    if (p->feat_prec < 0 || p->feat_prec > 2) return fail(MERF_E_INVALID, "feat_prec %d not in {0, 1, 2}", p->feat_prec);
     if (p->skip_mode != 0 && p->skip_mode != 1) return fail(MERF_E_INVALID, "skip_mode %d not in {0, 1}", p->skip_mode);
     if (p->tile_order != 0 && p->tile_order != 1)
         return fail(MERF_E_INVALID, "tile_order %d not in {0, 1}", p->tile_order);

@@ -76,6 +76,12 @@ __device__ __forceinline__ f16x2 codes0_0(uint32_t a, uint32_t b) {
     return as_f16x2(__builtin_amdgcn_perm(b, a, 0x0c040c00u));
 }
 
+// byte j of a and byte j of b
+template <int j>
+__device__ __forceinline__ f16x2 codes_jj(uint32_t a, uint32_t b) {
+    return as_f16x2(__builtin_amdgcn_perm(b, a, 0x0c000c00u | ((4u + j) << 16) | (uint32_t)j));
+}
+
 // Eq. 8 to float16 of a code given as the subnormal b 2^-24, with
 // a24 = 2^24 RN32(2m/255) (the scale the upload computes, times 2^24): the
 // product is b RN32(2m/255) exactly, so this is RN16(RN32(b a - m)), which
@@ -349,7 +355,7 @@ struct SampleResult {
 // One evaluated sample: gather, dequantise, decode.
 // All offsets are 32-bit (the upload keeps every array below 2 GiB) and are
 // added to uniform base pointers, so no 64-bit address arithmetic runs per lane.
-template <bool kFeatF16, typename S>
+template <int kFeat, typename S>
 __device__ __forceinline__ SampleResult eval_sample(const S &sc, float3 p, float delta) {
     const Footprint f = footprint(sc, p);
     const Texels x = gather(sc, f);
@@ -382,17 +388,21 @@ __device__ __forceinline__ SampleResult eval_sample(const S &sc, float3 p, float
     // and the weights of each present source sum to one, so
     // sum_i w_i q(b_i) = a * sum_i w_i b_i - n m exactly (n sources: 4 for
     // grid + planes).  The FP32 path
-    // (kFeatF16 = false) interpolates the codes and applies the affine map
+    // (kFeat = 0) interpolates the codes and applies the affine map
     // once per channel: the same real number with one convert and one FMA per
     // texel and channel; the two FP32 evaluations differ by rounding only
-    // (below 1e-6 relative).  The FP16 path dequantises every code to its
-    // correctly rounded float16 value first (deq_f16) and interpolates those
-    // values with FP32 weights and FP32 sums.
+    // (below 1e-6 relative).  The exact-FP16 path (kFeat = 1) dequantises
+    // every code to its correctly rounded float16 value first (deq_f16) and
+    // interpolates those values with FP32 weights and FP32 sums.  The
+    // FP16-interpolation path (kFeat = 2) computes density as the FP32 path
+    // does and interpolates the appearance channels from float16 operands:
+    // the weights rounded to float16, the codes exact, each pair of texels
+    // summed by one dot product with FP32 accumulation (v_dot2_f32_f16).
     // (a = d_scale or f_scale, n m = -d_off or -f_off, precomputed)
     const float md = sc.m_density, mf = sc.m_feature;
     // ---- density first (Sec. 6): appearance is read only when alpha != 0
     float s0 = 0.0f;
-    if constexpr (kFeatF16) {
+    if constexpr (kFeat == 1) {
         // a stand-in source (scene without grid or without planes) reads code
         // 0, whose float16 value is -m: its texels get weight 0 here, so that
         // the sum holds the present sources only (Eq. 5)
@@ -421,7 +431,24 @@ __device__ __forceinline__ SampleResult eval_sample(const S &sc, float3 p, float
         float sa[7];
 #pragma unroll
         for (int c = 0; c < 7; ++c) sa[c] = 0.0f;
-        if constexpr (kFeatF16) {
+        if constexpr (kFeat == 2) {
+            // texel pairs (2k, 2k + 1): their weights and the codes of one
+            // channel in one register each
+#pragma unroll
+            for (int k = 0; k < 10; ++k) {
+                const f16x2 wk = {(_Float16)w[2 * k], (_Float16)w[2 * k + 1]};
+                const uint32_t la = lo[2 * k], lb = lo[2 * k + 1], ha = hi[2 * k], hb = hi[2 * k + 1];
+                sa[0] = __builtin_amdgcn_fdot2(wk, codes_jj<1>(la, lb), sa[0], false);
+                sa[1] = __builtin_amdgcn_fdot2(wk, codes_jj<2>(la, lb), sa[1], false);
+                sa[2] = __builtin_amdgcn_fdot2(wk, codes_jj<3>(la, lb), sa[2], false);
+                sa[3] = __builtin_amdgcn_fdot2(wk, codes_jj<0>(ha, hb), sa[3], false);
+                sa[4] = __builtin_amdgcn_fdot2(wk, codes_jj<1>(ha, hb), sa[4], false);
+                sa[5] = __builtin_amdgcn_fdot2(wk, codes_jj<2>(ha, hb), sa[5], false);
+                sa[6] = __builtin_amdgcn_fdot2(wk, codes_jj<3>(ha, hb), sa[6], false);
+            }
+#pragma unroll
+            for (int c = 0; c < 7; ++c) sa[c] = fmaf(sa[c], sc.f_scale24, sc.f_off);
+        } else if constexpr (kFeat == 1) {
             const float af = sc.f_scale24;
 #pragma unroll
             for (int i = 0; i < 20; ++i) {
@@ -436,17 +463,24 @@ __device__ __forceinline__ SampleResult eval_sample(const S &sc, float3 p, float
                 sa[6] = fmaf(w[i], deq_f16(h13.y, af, mf), sa[6]);
             }
         } else {
+            // per texel pair: channel 2 of both texels from one permute, so
+            // 7 permutes or masks extract the 14 codes of the pair
 #pragma unroll
-            for (int i = 0; i < 20; ++i) {
-                const f16x2 l02 = codes02(lo[i]), l13 = codes13(lo[i]);
-                const f16x2 h02 = codes02(hi[i]), h13 = codes13(hi[i]);
-                sa[0] = fmaf(w[i], (float)l13.x, sa[0]);
-                sa[1] = fmaf(w[i], (float)l02.y, sa[1]);
-                sa[2] = fmaf(w[i], (float)l13.y, sa[2]);
-                sa[3] = fmaf(w[i], (float)h02.x, sa[3]);
-                sa[4] = fmaf(w[i], (float)h13.x, sa[4]);
-                sa[5] = fmaf(w[i], (float)h02.y, sa[5]);
-                sa[6] = fmaf(w[i], (float)h13.y, sa[6]);
+            for (int k = 0; k < 10; ++k) {
+                const f16x2 c2 = codes_jj<2>(lo[2 * k], lo[2 * k + 1]);
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const int i = 2 * k + t;
+                    const f16x2 l13 = codes13(lo[i]);
+                    const f16x2 h02 = codes02(hi[i]), h13 = codes13(hi[i]);
+                    sa[0] = fmaf(w[i], (float)l13.x, sa[0]);
+                    sa[1] = fmaf(w[i], (float)(t ? c2.y : c2.x), sa[1]);
+                    sa[2] = fmaf(w[i], (float)l13.y, sa[2]);
+                    sa[3] = fmaf(w[i], (float)h02.x, sa[3]);
+                    sa[4] = fmaf(w[i], (float)h13.x, sa[4]);
+                    sa[5] = fmaf(w[i], (float)h02.y, sa[5]);
+                    sa[6] = fmaf(w[i], (float)h13.y, sa[6]);
+                }
             }
 #pragma unroll
             for (int c = 0; c < 7; ++c) sa[c] = fmaf(sa[c], sc.f_scale24, sc.f_off);
@@ -831,7 +865,7 @@ struct MeasureArgs {
 
 // One wave renders local tile lt of camera cam (launch tile `tile`, used by
 // the measurement outputs only) of scene sc; lane = threadIdx.x.
-template <int kMode, int kMlpPrec, bool kFeatF16, bool kLevels, typename S, typename Cam>
+template <int kMode, int kMlpPrec, int kFeat, bool kLevels, typename S, typename Cam>
 __device__ __forceinline__ void render_tile(const S &sc, const Cam &cam, int lt, int tile,
                                             const TileParams tp, const MeasureArgs ma, float *lds, const int lane) {
     constexpr bool kStats = kMode >= 1, kPhase = kMode == 2;
@@ -1016,7 +1050,7 @@ __device__ __forceinline__ void render_tile(const S &sc, const Cam &cam, int lt,
         if (lane < total) {
             const int e = imap[lane];
             const float4 q = pq[e];
-            const SampleResult r = eval_sample<kFeatF16>(sc, make_float3(q.x, q.y, q.z), q.w);
+            const SampleResult r = eval_sample<kFeat>(sc, make_float3(q.x, q.y, q.z), q.w);
             rs[2 * lane] = make_float4(r.trans, r.sg[0], r.sg[1], r.sg[2]);
             rs[2 * lane + 1] = make_float4(r.sg[3], r.sg[4], r.sg[5], r.sg[6]);
         }
@@ -1102,7 +1136,7 @@ __device__ __forceinline__ void render_tile(const S &sc, const Cam &cam, int lt,
     }
 }
 
-template <int kMode, int kMlpPrec, bool kFeatF16, bool kLevels>
+template <int kMode, int kMlpPrec, int kFeat, bool kLevels>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_render(const DevScene sc, const RenderBatch rb) {
     __shared__ float lds[kLdsFloats<kMlpPrec>];
     const int slot = xcd_remap((int)blockIdx.x, rb.total_tiles);
@@ -1115,7 +1149,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     const DevCamera &cam = rb.cams[c];
     const TileParams tp = {rb.step, rb.inv_step, rb.t_min, rb.delta_mode};
     const MeasureArgs ma = {rb.stats, rb.rec, rb.rec_count, rb.rec_cap, rb.total_tiles, rb.phases};
-    render_tile<kMode, kMlpPrec, kFeatF16, kLevels>(sc, cam, tile - cam.tile_start, tile, tp, ma, lds,
+    render_tile<kMode, kMlpPrec, kFeat, kLevels>(sc, cam, tile - cam.tile_start, tile, tp, ma, lds,
                                                     (int)threadIdx.x);
 }
 
@@ -1140,7 +1174,7 @@ __device__ __forceinline__ int xcd_share_tile(int x, uint32_t i) {
 // The scene table and the launch descriptors are read through the constant
 // address space: they do not change during the launch, so the compiler reads
 // them with scalar loads and may repeat a load instead of holding its value.
-template <int kMlpPrec, bool kFeatF16, bool kLevels>
+template <int kMlpPrec, int kFeat, bool kLevels>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_render_served(
     ConstScene *__restrict__ table, ConstLaunch *__restrict__ launch, ServeCtl *__restrict__ ctl) {
     __shared__ float lds[kLdsFloats<kMlpPrec>];
@@ -1169,7 +1203,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
         ConstWork &w = L->work[c];
         const TileParams tp = {w.step, w.inv_step, w.t_min, w.delta_mode};
         const MeasureArgs ma = {nullptr, nullptr, nullptr, 0, 0, nullptr};
-        render_tile<0, kMlpPrec, kFeatF16, kLevels>(table[w.scene], w.cam, tile - w.cam.tile_start, tile, tp, ma, lds,
+        render_tile<0, kMlpPrec, kFeat, kLevels>(table[w.scene], w.cam, tile - w.cam.tile_start, tile, tp, ma, lds,
                                                     lane);
         __syncthreads();
         i = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl(nx, 0, 64));
@@ -1404,17 +1438,18 @@ __global__ void k_dequant(const uint8_t *__restrict__ codes, int64_t n, float m,
 
 }  // namespace
 
-template <int kMode, bool kFeatF16, bool kLevels>
+template <int kMode, int kFeat, bool kLevels>
 const void *render_kernel_mlp(int mlp_prec) {
-    return mlp_prec == 0 ? (const void *)k_render<kMode, 0, kFeatF16, kLevels>
-         : mlp_prec == 1 ? (const void *)k_render<kMode, 1, kFeatF16, kLevels>
-                         : (const void *)k_render<kMode, 2, kFeatF16, kLevels>;
+    return mlp_prec == 0 ? (const void *)k_render<kMode, 0, kFeat, kLevels>
+         : mlp_prec == 1 ? (const void *)k_render<kMode, 1, kFeat, kLevels>
+                         : (const void *)k_render<kMode, 2, kFeat, kLevels>;
 }
 
 template <int kMode, bool kLevels>
 const void *render_kernel_feat(const RenderBatch &rb) {
-    return rb.feat_prec ? render_kernel_mlp<kMode, true, kLevels>(rb.mlp_prec)
-                        : render_kernel_mlp<kMode, false, kLevels>(rb.mlp_prec);
+    return rb.feat_prec == 2 ? render_kernel_mlp<kMode, 2, kLevels>(rb.mlp_prec)
+         : rb.feat_prec == 1 ? render_kernel_mlp<kMode, 1, kLevels>(rb.mlp_prec)
+                             : render_kernel_mlp<kMode, 0, kLevels>(rb.mlp_prec);
 }
 
 template <int kMode>
@@ -1430,16 +1465,17 @@ const void *render_kernel(const RenderBatch &rb) {
 
 dim3 render_grid(const RenderBatch &rb) { return dim3((unsigned)rb.total_tiles); }
 
-template <bool kFeatF16, bool kLevels>
+template <int kFeat, bool kLevels>
 const void *served_kernel_mlp(int mlp_prec) {
-    return mlp_prec == 0 ? (const void *)k_render_served<0, kFeatF16, kLevels>
-         : mlp_prec == 1 ? (const void *)k_render_served<1, kFeatF16, kLevels>
-                         : (const void *)k_render_served<2, kFeatF16, kLevels>;
+    return mlp_prec == 0 ? (const void *)k_render_served<0, kFeat, kLevels>
+         : mlp_prec == 1 ? (const void *)k_render_served<1, kFeat, kLevels>
+                         : (const void *)k_render_served<2, kFeat, kLevels>;
 }
 
 const void *served_kernel(int mlp_prec, int feat_prec, int skip_mode) {
-    if (feat_prec) return skip_mode ? served_kernel_mlp<true, true>(mlp_prec) : served_kernel_mlp<true, false>(mlp_prec);
-    return skip_mode ? served_kernel_mlp<false, true>(mlp_prec) : served_kernel_mlp<false, false>(mlp_prec);
+    if (feat_prec == 2) return skip_mode ? served_kernel_mlp<2, true>(mlp_prec) : served_kernel_mlp<2, false>(mlp_prec);
+    if (feat_prec == 1) return skip_mode ? served_kernel_mlp<1, true>(mlp_prec) : served_kernel_mlp<1, false>(mlp_prec);
+    return skip_mode ? served_kernel_mlp<0, true>(mlp_prec) : served_kernel_mlp<0, false>(mlp_prec);
 }
 
 hipError_t launch_render_served(const DevScene *table, const ServeLaunch *launch, ServeCtl *ctl, int mlp_prec,

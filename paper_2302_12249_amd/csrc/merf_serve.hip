@@ -35,7 +35,7 @@ using Clock = std::chrono::steady_clock;
 namespace {
 
 constexpr int kMaxResident = 64;             // scene table slots of a server
-constexpr int kVariants = 12;                // MLP fp32 / fp16 / bf16  x  features fp32 / fp16  x  skip mode
+constexpr int kVariants = 18;                // MLP fp32 / fp16 / bf16  x  features (feat_prec 0..2)  x  skip mode
 constexpr int kGridClasses = 4;              // persistent grids of 64, 256, 1024, 4096 workgroups
 
 enum SceneState { kAbsent = 0, kLoading, kResident };
@@ -126,7 +126,7 @@ bool server_live(merf_server *s) {
     return s && g_servers.count(s);
 }
 
-int variant_of(const merf_render_params &p) { return p.mlp_prec + 3 * p.feat_prec + 6 * p.skip_mode; }
+int variant_of(const merf_render_params &p) { return p.mlp_prec + 3 * p.feat_prec + 9 * p.skip_mode; }
 
 // Persistent grid of a launch of n tiles: the largest class not above n (at
 // least the smallest), so that every workgroup has a tile to start with.

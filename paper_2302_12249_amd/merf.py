@@ -24,6 +24,9 @@ MAX_OCC_LEVELS = 4
 STATS_FIELDS = ["rays", "occ_lookups", "visited", "evaluated", "contributing", "terminated"]
 
 PREC = {"f32": 0, "fp32": 0, "f16": 1, "fp16": 1, "bf16": 2}
+# feature precision: fp32 interpolation of the codes, every code dequantised
+# to float16 first, or appearance interpolated from float16 operands
+FEAT = {"f32": 0, "fp32": 0, "f16": 1, "fp16": 1, "f16_interp": 2}
 
 
 class MerfError(RuntimeError):
@@ -199,7 +202,7 @@ def render_params(step: float = 0.0, t_min: float = 2e-4, delta_mode: int = 0, m
     p.struct_size = C.sizeof(merf_render_params)
     p.step, p.t_min, p.delta_mode = float(step), float(t_min), int(delta_mode)
     p.mlp_prec = PREC[mlp_prec] if isinstance(mlp_prec, str) else int(mlp_prec)
-    p.feat_prec = PREC[feat_prec] if isinstance(feat_prec, str) else int(feat_prec)
+    p.feat_prec = FEAT[feat_prec] if isinstance(feat_prec, str) else int(feat_prec)
     p.skip_mode = SKIP[skip] if isinstance(skip, str) else int(skip)
     p.tile_order = ORDER[order] if isinstance(order, str) else int(order)
     p.stats_dev = stats_ptr

@@ -36,7 +36,8 @@ def scene(request):
     return synth.preset_scene(request.param)
 
 
-@pytest.mark.parametrize("kw", [{}, {"delta_mode": 1}, {"mlp_prec": "bf16", "feat_prec": "f16"}])
+@pytest.mark.parametrize("kw", [{}, {"delta_mode": 1}, {"mlp_prec": "bf16", "feat_prec": "f16"},
+                                {"mlp_prec": "f16", "feat_prec": "f16_interp"}])
 def test_edge_rays_match_oracle(torch, merf, scene, kw):
     names, cams = edge_cameras()
     say(f"{scene.name}: {len(cams)} edge-case cameras {kw}")

@@ -332,20 +332,26 @@ def test_precision_mlp_full_sampled(torch, merf, full_scene, prec):
     check(gpu[rows_of(cams, 54, 7)], ref, st["fragile"], f"full mlp {prec}", min_psnr=MIN_PSNR_DB)
 
 
+@pytest.mark.parametrize("feat", ["f16", "f16_interp"])
 @pytest.mark.parametrize("mlp", ["f32", "f16", "bf16"])
-def test_fp16_features_tiny(torch, merf, tiny_scene, tiny_cams, mlp):
-    say(f"tiny, features dequantised to fp16, MLP {mlp}")
-    gpu = gpu_render(torch, merf, tiny_scene, tiny_cams, feat_prec="f16", mlp_prec=mlp)
+def test_fp16_features_tiny(torch, merf, tiny_scene, tiny_cams, mlp, feat):
+    say(f"tiny, features {feat}, MLP {mlp}")
+    gpu = gpu_render(torch, merf, tiny_scene, tiny_cams, feat_prec=feat, mlp_prec=mlp)
     ref, st = oracle.render(tiny_scene, tiny_cams)
-    check(gpu, ref, st["fragile"], f"tiny feat f16 mlp {mlp}", min_psnr=MIN_PSNR_DB)
+    check(gpu, ref, st["fragile"], f"tiny feat {feat} mlp {mlp}", min_psnr=MIN_PSNR_DB)
+    if feat == "f16_interp":
+        # density is summed in fp32 as in the fp32 path: the same alpha bit for bit
+        f32 = gpu_render(torch, merf, tiny_scene, tiny_cams, mlp_prec=mlp)
+        assert np.array_equal(gpu[:, 3], f32[:, 3])
 
 
-def test_fp16_features_full_sampled(torch, merf, full_scene):
-    say("full 1080p, features fp16 + MLP fp16 (every 54th row checked)")
+@pytest.mark.parametrize("feat", ["f16", "f16_interp"])
+def test_fp16_features_full_sampled(torch, merf, full_scene, feat):
+    say(f"full 1080p, features {feat} + MLP fp16 (every 54th row checked)")
     cams = synth.full_camera()
-    gpu = gpu_render(torch, merf, full_scene, cams, feat_prec="f16", mlp_prec="f16")
+    gpu = gpu_render(torch, merf, full_scene, cams, feat_prec=feat, mlp_prec="f16")
     ref, st = oracle.render(full_scene, cams, rows_stride=54, row_offset=7)
-    check(gpu[rows_of(cams, 54, 7)], ref, st["fragile"], "full feat f16 mlp f16", min_psnr=MIN_PSNR_DB)
+    check(gpu[rows_of(cams, 54, 7)], ref, st["fragile"], f"full feat {feat} mlp f16", min_psnr=MIN_PSNR_DB)
 
 
 def test_precision_orbit_views_sampled(torch, merf, full_scene):
@@ -353,12 +359,13 @@ def test_precision_orbit_views_sampled(torch, merf, full_scene):
     cams = synth.orbit_cameras(16, w=480, h=270)
     ref, st = oracle.render(full_scene, cams, rows_stride=9, row_offset=4)
     sel = rows_of(cams, 9, 4)
-    for mlp, feat in (("f32", "f32"), ("f16", "f32"), ("bf16", "f32"), ("f16", "f16"), ("bf16", "f16")):
+    for mlp, feat in (("f32", "f32"), ("f16", "f32"), ("bf16", "f32"), ("f16", "f16"), ("bf16", "f16"),
+                      ("f32", "f16_interp"), ("f16", "f16_interp"), ("bf16", "f16_interp")):
         gpu = gpu_render(torch, merf, full_scene, cams, mlp_prec=mlp, feat_prec=feat)
         check(gpu[sel], ref, st["fragile"], f"orbit mlp {mlp} feat {feat}", min_psnr=MIN_PSNR_DB)
 
 
-@pytest.mark.parametrize("feat", ["f32", "f16"])
+@pytest.mark.parametrize("feat", ["f32", "f16", "f16_interp"])
 def test_planes_only_variant(torch, merf, tiny_scene, tiny_cams, feat):
     say(f"tiny scene without its 3D grid (planes only), features {feat}")
     po = synth.planes_only(tiny_scene)
@@ -367,7 +374,7 @@ def test_planes_only_variant(torch, merf, tiny_scene, tiny_cams, feat):
     check(gpu, ref, st["fragile"], f"planes only, features {feat}")
 
 
-@pytest.mark.parametrize("feat", ["f32", "f16"])
+@pytest.mark.parametrize("feat", ["f32", "f16", "f16_interp"])
 def test_grid_only_variant(torch, merf, tiny_cams, feat):
     say(f"grid-only scene (L = 128, no planes), features {feat}")
     go = synth.grid_only_scene(128, 0.08, seed=4)

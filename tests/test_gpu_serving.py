@@ -74,8 +74,9 @@ def test_mix_equals_alone(torch, merf, scenes, use_graphs):
         torch.cuda.synchronize()
         tickets = []
         steps = [0.0 if i % 4 else 1.0 / 48 for i in range(len(cams))]   # default step 4/R, or a coarser one
+        feats = ["f16_interp" if i % 6 == 5 else "f32" for i in range(len(cams))]
         for i in range(len(cams)):
-            p = merf.render_params(mlp_prec=prec[i], step=steps[i])
+            p = merf.render_params(mlp_prec=prec[i], step=steps[i], feat_prec=feats[i])
             tickets.append(srv.submit(ids[scene_of[i]], arr, i, outs[i].data_ptr(), p))
         lats = [srv.wait(t)[0] for t in tickets]
         st = srv.stats()
@@ -89,7 +90,7 @@ def test_mix_equals_alone(torch, merf, scenes, use_graphs):
         for i in range(len(cams)):
             r = merf.Renderer(scenes[scene_of[i]])
             try:
-                alone = r.render(cams.subset(i), mlp_prec=prec[i], step=steps[i])
+                alone = r.render(cams.subset(i), mlp_prec=prec[i], step=steps[i], feat_prec=feats[i])
                 torch.cuda.synchronize()
                 alone = alone.cpu().numpy()
             finally:
