@@ -134,9 +134,9 @@ typedef struct {
                                              each tile to their first occupied sample;
                                              calls on a device allocate up to 64 work
                                              buffers of 672 KB, kept until the process
-                                             ends; with all 64 in flight, a call waits
-                                             for the oldest to finish), plain order
-                                             otherwise; 1 = plain order */
+                                             ends; with all 64 in flight, the call
+                                             keeps the plain order and never waits),
+                                             plain order otherwise; 1 = plain order */
     uint64_t *stats_dev;                  /* NULL, or device uint64[8] to which the render
                                              ADDS: [0] rays, [1] occupancy lookups
                                              (skip_mode 0: distance-grid lookups),

@@ -247,13 +247,12 @@ hipStream_t order_stream(int device) {
 
 // Index of a free buffer of the device, or -1 (caller holds g_order_mutex).
 int order_buffer(int device) {
-    int oldest = -1, n = 0;
+    int n = 0;
     for (int i = 0; i < (int)g_order_bufs.size(); ++i) {
         const OrderBuf &b = g_order_bufs[i];
         if (b.device != device) continue;
         ++n;
         if (b.last_use == 0 || hipEventQuery(b.done) == hipSuccess) return i;
-        if (oldest < 0 || b.last_use < g_order_bufs[oldest].last_use) oldest = i;
     }
     if (n < kOrderBufs) {
         OrderBuf b{device, nullptr, nullptr, nullptr, nullptr, nullptr, 0};
@@ -270,7 +269,8 @@ int order_buffer(int device) {
         if (b.order) (void)hipFree(b.order);
         if (b.ready) (void)hipEventDestroy(b.ready);
     }
-    if (oldest >= 0 && hipEventSynchronize(g_order_bufs[oldest].done) == hipSuccess) return oldest;
+    // every buffer of the device is in flight: the launch keeps the plain
+    // order (the same image) rather than blocking the caller on the oldest
     return -1;
 }
 

@@ -269,7 +269,8 @@ def test_tile_order_concurrent_streams(torch, merf, full_scene):
 
 def test_tile_order_many_frames_in_flight(torch, merf, full_scene):
     say("full 1080p view rendered 80 times back to back without waiting (more frames in flight than "
-        "tile-order work buffers, so buffers are reused and the host waits for the oldest)")
+        "tile-order work buffers: buffers are reused, and calls that find all of them in flight keep the "
+        "plain order)")
     cams = synth.full_camera()
     r = merf.Renderer(full_scene)
     try:
