@@ -101,15 +101,18 @@ def test_mix_equals_alone(torch, merf, scenes, use_graphs):
 
 
 def test_served_outputs_match_oracle(torch, merf, scenes):
-    say("serving: 24 uneven requests over 3 scenes (fp32 / fp16 / bf16 MLP) against the FP64 oracle")
+    say("serving: 24 uneven requests over 3 scenes (fp32 / fp16 / bf16 MLP, fp32 or fp16-interpolated "
+        "features) against the FP64 oracle")
     cams, scene_of, prec = request_mix(24, seed=13)
+    feats = ["f16_interp" if i % 3 == 1 else "f32" for i in range(len(cams))]
     arr = merf.camera_array(cams)
     srv = merf.Server(slots=3, max_batch=8, use_graphs=True)
     try:
         ids = [srv.add_scene(s) for s in scenes]
         outs = [torch.full((int(w) * int(h), 4), float("nan"), device="cuda") for w, h in cams.size]
         torch.cuda.synchronize()
-        tickets = [srv.submit(ids[scene_of[i]], arr, i, outs[i].data_ptr(), merf.render_params(mlp_prec=prec[i]))
+        tickets = [srv.submit(ids[scene_of[i]], arr, i, outs[i].data_ptr(),
+                              merf.render_params(mlp_prec=prec[i], feat_prec=feats[i]))
                    for i in range(len(cams))]
         for t in tickets:
             srv.wait(t)

@@ -71,6 +71,10 @@ def test_noalloc_matches_render_on_two_calls(torch, merf):
         r4, g4 = _both(torch, merf, handle, small, order="plain")
         assert np.array_equal(r4.view(np.uint32), g4.view(np.uint32))
         assert np.array_equal(r4.view(np.uint32), got2.view(np.uint32))
+        # the reduced-precision kernel variants take the same path
+        say("noalloc: fp16 interpolation with the bf16 MLP, tile order")
+        r5, g5 = _both(torch, merf, handle, cams, feat_prec="f16_interp", mlp_prec="bf16")
+        assert np.array_equal(r5.view(np.uint32), g5.view(np.uint32))
     finally:
         merf.merf_free(handle)
 
