@@ -226,7 +226,9 @@ size_t merf_scene_bytes(merf_scene_t s);
  *     interpolates the codes of each source and applies Eq. 8's affine map
  *     once per channel, which equals the interpolation of the dequantised
  *     values in exact arithmetic because the weights of each source sum to 1
- *     (the two differ by float32 rounding only).
+ *     (the two differ by float32 rounding only).  The fp16-interpolation
+ *     path (feat_prec = 2) applies the same affine map after interpolating
+ *     the codes with float16 weights.
  * Asynchronous on hip_stream.
  * Errors: MERF_E_INVALID for n < 0, NULL buffers, m <= 0 or a bad prec.
  */
