@@ -131,7 +131,9 @@ typedef struct {
                                              same image either way: 0 = estimated
                                              heaviest first for launches of 6144 to
                                              131072 tiles (a prepass marches 4 rays of
-                                             each tile to their first occupied sample;
+                                             each tile and, up to 65536 tiles, counts
+                                             the samples they evaluate before
+                                             terminating, up to 4 each;
                                              calls on a device allocate up to 64 work
                                              buffers of 672 KB, kept until the process
                                              ends; with all 64 in flight, the call

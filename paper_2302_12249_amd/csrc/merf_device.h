@@ -27,7 +27,7 @@ constexpr int kOctMaxRes = 256;                  // up to this r_f the grid has 
 // to gain nothing below) or more than kOrderMaxTiles (the work buffers' size;
 // there the end of the launch is a small part of it) keep the plain order.
 constexpr int kCostRays = 4;
-constexpr int kCostKeys = kCostRays + 1;         // key = rays of the tile that reach occupied space
+constexpr int kCostKeys = kCostRays + 1;         // keys 0 .. 4: classes of estimated effort (k_tile_cost)
 constexpr int kOrderMinTiles = 6144;
 constexpr int kOrderMaxTiles = 1 << 17;
 

@@ -1219,21 +1219,33 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 }
 
 // Tile cost for the launch order.  kCostRays rays of every 8x8 tile (pixels
-// (2,2), (5,2), (2,5) and (5,5) of the tile, clamped to the image) march
-// through empty space, as the renderer does, to their first occupied sample;
-// the key of a tile is the number of its rays that reach one.  Only rays
-// that reach occupied space gather, shade and composite, so tiles with higher
-// keys take longer; a march longer than kCostSteps steps also counts as a hit.
+// (2,2), (5,2), (2,5) and (5,5) of the tile, clamped to the image) march as
+// the renderer does, through empty space to their first occupied sample.
+// With kEffort they go on through occupied space, where the opacity of each
+// evaluated sample (its density; the rest of the shading is not needed) is
+// composited, until the ray terminates (T < t_min), ends, or has evaluated
+// kCostEval samples.  The effort E of a tile is the sum of its rays'
+// evaluated samples (a march still running after kCostSteps steps counts
+// one); its key is 0 for E = 0 and 1 + [E >= 2 kCostRays] +
+// [E >= 3 kCostRays] + [E >= 4 kCostRays] otherwise: rays that reach no
+// occupied space only march, rays that terminate within a sample or two
+// shade little, and rays that keep shading cost the most.  Without kEffort
+// the key is the number of rays that reach occupied space (the cheaper
+// prepass, for launches so large that the end of the launch is a small part
+// of it).
 constexpr int kCostSteps = 64;
+constexpr int kCostEval = 4;
+constexpr int kEffortMaxTiles = 1 << 16;
 constexpr int kGroupTiles = 64 / kCostRays;                   // tiles of one k_tile_cost wave
 constexpr int kCountBits = kGroupTiles < 32 ? 5 : 7;           // a group's count of one key
 constexpr int kScanBits = 64 / kCostKeys;                      // a workgroup's count of one key
 static_assert(kCostKeys * kCountBits <= 32 && (uint64_t)64 * kGroupTiles < (1ull << kScanBits), "count fields");
+template <bool kEffort>
 __global__ __launch_bounds__(64) void k_tile_cost(const DevScene sc, const RenderBatch rb, uint8_t *__restrict__ keys,
                                                   uint32_t *__restrict__ group_counts) {
     const int g = (int)blockIdx.x * 64 + (int)threadIdx.x;
     const int tile = g / kCostRays, sub = g % kCostRays;
-    bool hit = false;
+    int ev = 0;                                               // samples this ray evaluated
     if (tile < rb.total_tiles) {
         const DevCamera &cam = rb.cams[camera_of(rb, tile)];
         const int lt = tile - cam.tile_start;
@@ -1246,14 +1258,11 @@ __global__ __launch_bounds__(64) void k_tile_cost(const DevScene sc, const Rende
         const Candidates C = make_candidates(o, d);
         const float c1 = next_candidate(C, 0.0f);
         open_segment(o, d, 0.0f, region_at(o, d, c1 < kInf ? 0.5f * c1 : 1.0f), istep, sc.dist_oct_stride, s);
-        int nseg = 1;
-        hit = true;
-        for (int it = 0; it < kCostSteps; ++it) {
+        int nseg = 1, it = 0;
+        float T = 1.0f;
+        for (; it < kCostSteps; ++it) {
             if (s.k >= s.n) {
-                if (!(s.tb < kInf) || nseg >= 8) {
-                    hit = false;
-                    break;
-                }
+                if (!(s.tb < kInf) || nseg >= 8) break;
                 open_segment(o, d, s.tb, s.reg_next, istep, sc.dist_oct_stride, s);
                 ++nseg;
                 continue;
@@ -1263,13 +1272,34 @@ __global__ __launch_bounds__(64) void k_tile_cost(const DevScene sc, const Rende
             const float um = 0.5f * (u0 + u1);
             const float3 p = make_float3(fmaf(um, s.e.x, s.A.x), fmaf(um, s.e.y, s.A.y), fmaf(um, s.e.z, s.A.z));
             float ue;
-            if (dist_lookup(sc, s, p, ue) == 0) break;
-            s.k = skip_past(s, ue, istep);
+            if (dist_lookup(sc, s, p, ue) == 0) {
+                // an occupied sample: the renderer evaluates it
+                if (!kEffort) {
+                    ev = 1;
+                    break;
+                }
+                T *= eval_sample<0>(sc, p, u1 - u0).trans;
+                if (++ev >= kCostEval || T < rb.t_min) break;
+                ++s.k;
+            } else {
+                s.k = skip_past(s, ue, istep);
+            }
         }
+        if (it == kCostSteps && ev == 0) ev = 1;
     }
-    // the kCostRays rays of a tile are consecutive lanes
-    const uint64_t b = __ballot(hit);
-    const int key = __popcll((b >> ((int)threadIdx.x & ~(kCostRays - 1))) & ((1ull << kCostRays) - 1));
+    // the kCostRays rays of a tile are consecutive lanes: their effort from
+    // the bits of ev (at most kCostEval < 8)
+    static_assert(kCostEval < 8 && kCostRays * kCostEval < 256, "effort bits");
+    const uint64_t tm = ((1ull << kCostRays) - 1) << ((int)threadIdx.x & ~(kCostRays - 1));
+    int key;
+    if (kEffort) {
+        int effort = 0;
+#pragma unroll
+        for (int bit = 0; bit < 3; ++bit) effort += __popcll(__ballot((ev >> bit) & 1) & tm) << bit;
+        key = effort == 0 ? 0 : 1 + (effort >= 2 * kCostRays) + (effort >= 3 * kCostRays) + (effort >= 4 * kCostRays);
+    } else {
+        key = __popcll(__ballot(ev > 0) & tm);
+    }
     const bool head = tile < rb.total_tiles && sub == 0;
     if (head) keys[tile] = (uint8_t)key;
     // the keys of the wave's kGroupTiles tiles (a group), counted per key in
@@ -1498,7 +1528,10 @@ hipError_t launch_tile_order(const DevScene &sc, const RenderBatch &rb, uint8_t 
                              int32_t *order, hipStream_t stream) {
     if (rb.total_tiles <= 0 || rb.total_tiles > kOrderMaxTiles) return hipErrorInvalidValue;
     const int groups = (rb.total_tiles + kGroupTiles - 1) / kGroupTiles;
-    hipLaunchKernelGGL(k_tile_cost, dim3((unsigned)groups), dim3(64), 0, stream, sc, rb, keys, group_counts);
+    if (rb.total_tiles <= kEffortMaxTiles)
+        hipLaunchKernelGGL(k_tile_cost<true>, dim3((unsigned)groups), dim3(64), 0, stream, sc, rb, keys, group_counts);
+    else
+        hipLaunchKernelGGL(k_tile_cost<false>, dim3((unsigned)groups), dim3(64), 0, stream, sc, rb, keys, group_counts);
     hipLaunchKernelGGL(k_tile_order, dim3((unsigned)((groups + 63) / 64)), dim3(64), 0, stream, keys, group_counts,
                        rb.total_tiles, order);
     return hipGetLastError();
