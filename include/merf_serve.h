@@ -25,12 +25,13 @@
  *    max_batch -- into one launch.  Requests that arrive while others run
  *    are admitted as soon as a slot frees up, and the launches of different
  *    slots overlap on the device.
- *  - Persistent launches: a served launch has a fixed number of workgroups
- *    (64, 256, 1024 or 4096, the largest not above its tile count) that take
- *    8x8 tiles from a device-side counter per XCD until the launch's tiles
- *    are done.  It reads its work descriptors (per request: scene slot,
- *    camera, output, march parameters) and a device table of the resident
- *    scenes from device memory.  With use_graphs, each slot captures one
+ *  - Launch classes: a served launch has a fixed number of workgroups,
+ *    64 << 2c for c = 0 .. 6 (64 to 262144): the smallest class with a
+ *    workgroup for each of its 8x8 tiles.  A launch of more tiles is
+ *    persistent: 4096 workgroups go on taking tiles from a device-side
+ *    counter per XCD until the launch's tiles are done.  It reads its work
+ *    descriptors (per request: scene slot, camera, output, march parameters)
+ *    and a device table of the resident scenes from device memory.  With use_graphs, each slot captures one
  *    hipGraph per kernel variant and grid size -- a copy of the descriptors
  *    into device memory, then the kernel -- and replays it unchanged.
  *

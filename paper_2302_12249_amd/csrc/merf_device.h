@@ -111,8 +111,8 @@ struct RenderBatch {
     DevCamera cams[kCamsPerLaunch];
 };
 
-// Served launches (merf_serve.hip): one persistent launch renders requests
-// of several resident scenes.  The descriptors live in device memory, so a
+// Served launches (merf_serve.hip): one launch renders requests of several
+// resident scenes.  The descriptors live in device memory, so a
 // captured graph replays a launch unchanged (its first node copies the
 // descriptors in).
 struct ServeWork {
@@ -127,15 +127,14 @@ struct ServeLaunch {
 };
 // Workgroup b of a served launch of G workgroups takes tiles from the share
 // of XCD x = b % 8 (the runs of 4 consecutive tiles that xcd_remap deals to
-// that XCD): first position b / 8, then G / 8 + the positions it takes from
-// the XCD's counter, until the share is exhausted.  Each counter has a
-// 256-byte line of its own.  Zero before a slot's first launch; every launch
-// leaves it zero.
+// that XCD): first position b / 8, then, when the launch has more than G / 8
+// positions per XCD, G / 8 + the positions it takes from the XCD's counter,
+// until the share is exhausted.  Each counter has a 256-byte line of its
+// own, zeroed before each launch that may take positions from it.
 constexpr int kXcds = 8;
 constexpr int kCtlStride = 64;                   // uint32 per counter line
 struct ServeCtl {
     uint32_t next[kXcds * kCtlStride];           // next[x * kCtlStride]: positions taken by XCD x
-    uint32_t done[kCtlStride];                   // done[0]: workgroups finished
 };
 
 // Slots of RenderBatch::phases (uint64 each, summed over the waves of a launch).
@@ -163,6 +162,8 @@ hipError_t launch_render(const DevScene &sc, const RenderBatch &rb, hipStream_t 
 // ServeWork::scene), in the kernel variant of (mlp_prec, feat_prec,
 // skip_mode); ctl (device) is the slot's control block.
 const void *served_kernel(int mlp_prec, int feat_prec, int skip_mode);
+// Zero the counters of a served launch's control block.
+hipError_t launch_zero_ctl(ServeCtl *ctl, hipStream_t stream);
 hipError_t launch_render_served(const DevScene *table, const ServeLaunch *launch, ServeCtl *ctl, int mlp_prec,
                                 int feat_prec, int skip_mode, int grid, hipStream_t stream);
 // Heaviest-first tile order of a launch: keys (uint8 [kOrderMaxTiles])

@@ -1153,16 +1153,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
                                                     (int)threadIdx.x);
 }
 
-// Served launch (persistent): each workgroup takes tiles from its XCD's
-// share of the launch (XCD x = blockIdx % 8 holds the runs of kXcdChunk
-// consecutive tiles that xcd_remap deals to x) until the share is exhausted,
-// so neighbouring tiles still share an L2 and the launch shape does not
-// depend on the requests.  A workgroup's first tile is fixed by its index;
-// it asks the XCD's counter for the next one as it starts each tile, so the
-// atomic's round trip overlaps the render.  Each tile belongs to one request,
-// which names its camera, march parameters and scene (a slot of the server's
-// scene table).  The last workgroup to finish zeroes the control block for
-// the next launch.
+// Served launch: workgroup b renders position b / 8 of its XCD's share of
+// the launch (XCD x = blockIdx % 8 holds the runs of kXcdChunk consecutive
+// tiles that xcd_remap deals to x), so neighbouring tiles still share an L2.
+// The grid is a fixed class (the server captures one graph per class), the
+// smallest that gives every tile a workgroup of its own; workgroups past the
+// launch's tiles exit at once.  A launch larger than the largest such class
+// is persistent (a grid of the device's wave slots): its workgroups go on
+// taking positions from the XCD's
+// counter, asking for the next one as they start each tile so that the
+// atomic's round trip overlaps the render, until the share is exhausted; the
+// counters are zeroed before such a launch (k_zero_ctl).  (A 4096-workgroup
+// persistent grid rendered a 1080p request 13% slower than one workgroup per
+// tile, and 5% slower once its workgroups no longer counted themselves out
+// on one shared counter at the end.)  Each tile belongs to one request, which
+// names its camera, march parameters and scene (a slot of the server's scene
+// table).
 typedef const __attribute__((address_space(4))) DevScene ConstScene;
 typedef const __attribute__((address_space(4))) ServeLaunch ConstLaunch;
 typedef const __attribute__((address_space(4))) ServeWork ConstWork;
@@ -1182,6 +1188,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     const uint32_t base = gridDim.x / kXcds;      // positions handed out by workgroup index
     uint32_t *counter = ctl->next + x * kCtlStride;
     uint32_t i = blockIdx.x / kXcds;
+    // a launch with more positions per XCD than the grid gives it loops
+    const bool loops = base < (uint32_t)((launch->total_tiles + kXcds - 1) / kXcds);
     for (;;) {
         // nothing is carried from one tile to the next: opaque copies of the
         // lane id and the launch pointer keep the compiler from hoisting
@@ -1195,7 +1203,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
         const int tile = xcd_share_tile(x, i);
         if (i >= (uint32_t)n || tile >= n) break;
         uint32_t nx = 0;                           // the next position, in flight during the render
-        if (lane == 0) nx = base + atomicAdd(counter, 1u);
+        if (loops && lane == 0) nx = base + atomicAdd(counter, 1u);
         int c = 0;
 #pragma unroll
         for (int k = 1; k < kCamsPerLaunch; ++k)
@@ -1205,17 +1213,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
         const MeasureArgs ma = {nullptr, nullptr, nullptr, 0, 0, nullptr};
         render_tile<0, kMlpPrec, kFeat, kLevels>(table[w.scene], w.cam, tile - w.cam.tile_start, tile, tp, ma, lds,
                                                     lane);
+        if (!loops) break;
         __syncthreads();
         i = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl(nx, 0, 64));
     }
-    if (threadIdx.x == 0) {
-        __threadfence();
-        if (atomicAdd(ctl->done, 1u) == gridDim.x - 1) {
-#pragma unroll
-            for (int k = 0; k < kXcds; ++k) atomicExch(ctl->next + k * kCtlStride, 0u);
-            atomicExch(ctl->done, 0u);
-        }
-    }
+}
+
+// Zero a served launch's counters (a node of its own before the launch, so
+// that no workgroup of the launch has to find out that it is the last one).
+__global__ __launch_bounds__(64) void k_zero_ctl(ServeCtl *__restrict__ ctl) {
+    if ((int)threadIdx.x < kXcds) ctl->next[threadIdx.x * kCtlStride] = 0u;
 }
 
 // Tile cost for the launch order.  kCostRays rays of every 8x8 tile (pixels
@@ -1506,6 +1513,11 @@ const void *served_kernel(int mlp_prec, int feat_prec, int skip_mode) {
     if (feat_prec == 2) return skip_mode ? served_kernel_mlp<2, true>(mlp_prec) : served_kernel_mlp<2, false>(mlp_prec);
     if (feat_prec == 1) return skip_mode ? served_kernel_mlp<1, true>(mlp_prec) : served_kernel_mlp<1, false>(mlp_prec);
     return skip_mode ? served_kernel_mlp<0, true>(mlp_prec) : served_kernel_mlp<0, false>(mlp_prec);
+}
+
+hipError_t launch_zero_ctl(ServeCtl *ctl, hipStream_t stream) {
+    hipLaunchKernelGGL(k_zero_ctl, dim3(1), dim3(64), 0, stream, ctl);
+    return hipGetLastError();
 }
 
 hipError_t launch_render_served(const DevScene *table, const ServeLaunch *launch, ServeCtl *ctl, int mlp_prec,

@@ -5,10 +5,11 @@
 // when a request needs them, evicting the least recently used scenes that no
 // earlier request needs.  A worker thread continuously batches waiting
 // requests of resident scenes -- any scenes, any image sizes -- into
-// persistent launches of the served render kernel on several HIP streams; a
-// launch reads its work descriptors and the scene table from device memory,
-// so each slot replays one captured graph per kernel variant and grid size
-// without changing it.  A loader thread admits scenes as memory frees up.
+// launches of the served render kernel on several HIP streams, with a grid
+// from a fixed set of classes (persistent beyond the largest); a launch reads
+// its work descriptors and the scene table from device memory, so each slot
+// replays one captured graph per kernel variant and grid class without
+// changing it.  A loader thread admits scenes as memory frees up.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,7 +37,11 @@ namespace {
 
 constexpr int kMaxResident = 64;             // scene table slots of a server
 constexpr int kVariants = 18;                // MLP fp32 / fp16 / bf16  x  features (feat_prec 0..2)  x  skip mode
-constexpr int kGridClasses = 4;              // persistent grids of 64, 256, 1024, 4096 workgroups
+// Grid classes: 64 << 2c workgroups for c = 0 .. 6 (64 to 262144, one tile
+// each), and a persistent grid of 4096 workgroups (the device's wave slots at
+// four waves per SIMD) for larger launches.
+constexpr int kGridClasses = 8;
+constexpr int kPersistentGrid = 4096;
 
 enum SceneState { kAbsent = 0, kLoading, kResident };
 
@@ -128,14 +133,14 @@ bool server_live(merf_server *s) {
 
 int variant_of(const merf_render_params &p) { return p.mlp_prec + 3 * p.feat_prec + 9 * p.skip_mode; }
 
-// Persistent grid of a launch of n tiles: the largest class not above n (at
-// least the smallest), so that every workgroup has a tile to start with.
+// Grid of a launch of n tiles: the smallest class with a workgroup for every
+// tile, or the persistent class, whose workgroups loop, for larger launches.
 int grid_class(int64_t n) {
     int c = 0;
-    while (c + 1 < kGridClasses && n >= (int64_t)64 << (2 * (c + 1))) ++c;
+    while (c + 1 < kGridClasses && n > (int64_t)64 << (2 * c)) ++c;
     return c;
 }
-int grid_of_class(int c) { return 64 << (2 * c); }
+int grid_of_class(int c) { return c == kGridClasses - 1 ? kPersistentGrid : 64 << (2 * c); }
 
 // A queued request may be dispatched when its scene is resident, unless the
 // scene is being emptied to admit an older request's scene.
@@ -153,6 +158,8 @@ hipError_t launch_slot(merf_server *S, Slot &sl, const merf_render_params &p, in
     const int grid = grid_of_class(gclass);
     auto enqueue = [&]() {
         hipError_t e = hipMemcpyAsync(sl.desc_dev, sl.staging, sizeof(ServeLaunch), hipMemcpyHostToDevice, sl.stream);
+        // only a launch of the largest class can take positions from the counters
+        if (e == hipSuccess && gclass == kGridClasses - 1) e = launch_zero_ctl(sl.ctl_dev, sl.stream);
         if (e == hipSuccess)
             e = launch_render_served(S->table_dev, sl.desc_dev, sl.ctl_dev, p.mlp_prec, p.feat_prec, p.skip_mode, grid,
                                      sl.stream);
