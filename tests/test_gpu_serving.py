@@ -262,6 +262,40 @@ def test_admission_while_serving_from_threads(torch, merf, scenes):
         srv.close()
 
 
+def test_launch_beyond_largest_class_is_persistent(torch, merf):
+    """A launch of more tiles than the largest one-workgroup-per-tile class
+    (262144) runs on the persistent grid, whose workgroups take tiles from
+    per-XCD counters that a kernel node zeroes before each launch: two such
+    launches in a row, then a small one, each request bitwise as rendered
+    alone."""
+    say("serving: two launches of one 8192x2176 request (278528 tiles each, persistent grid), then a small one")
+    scene = synth.preset_scene("tiny", seed=5)
+    sizes = [(8192, 2176)] * 2 + [(96, 64)]
+    cams = synth.random_cameras(len(sizes), seed=29, sizes=sizes, inside=2.5)
+    arr = merf.camera_array(cams)
+    srv = merf.Server(slots=1, max_batch=1, use_graphs=True)
+    try:
+        sid = srv.add_scene(scene)
+        outs = [torch.full((w * h, 4), float("nan"), device="cuda") for w, h in sizes]
+        torch.cuda.synchronize()
+        tickets = [srv.submit(sid, arr, i, outs[i].data_ptr(), merf.render_params()) for i in range(len(sizes))]
+        for t in tickets:
+            srv.wait(t)
+        st = srv.stats()
+        say(f"  launches {st['launches']} (graph {st['graph_launches']})")
+        assert st["completed"] == len(sizes) and st["launches"] == 3
+        r = merf.Renderer(scene)
+        try:
+            for i in range(len(sizes)):
+                alone = r.render(cams.subset(i))
+                torch.cuda.synchronize()
+                assert torch.equal(outs[i], alone), i
+        finally:
+            r.close()
+    finally:
+        srv.close()
+
+
 def test_busy_scene_cannot_be_removed(torch, merf, scenes):
     say("serving: removing a scene with queued work is refused")
     srv = merf.Server(slots=1, max_batch=1)
