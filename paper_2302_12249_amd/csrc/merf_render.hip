@@ -18,11 +18,16 @@
 //   4. evaluated samples are parked in LDS; the wave shades up to 64 parked
 //      samples at once, whoever's they are: gather the 3D grid (trilinear,
 //      one brick per sample thanks to the apron) and the three planes
-//      (bilinear), dequantise each code (Eq. 8), sum (Eq. 5), decode
-//      (Eq. 6) -- density first, appearance only when alpha != 0; each lane
-//      then composites its own samples in ray order (Eq. 1-2);
+//      (bilinear), dequantise (Eq. 8; the fp32 path applies it to the
+//      interpolated codes, the same value up to rounding), sum (Eq. 5),
+//      decode (Eq. 6) -- density first, appearance only when alpha != 0;
+//      each lane then composites its own samples in ray order (Eq. 1-2);
 //   5. marching stops when the transmittance drops below t_min (Sec. 6);
 //   6. the deferred MLP h(C_d, F, d) runs once per pixel (Eq. 3, App. B).
+// Before a launch, a prepass (k_tile_cost, k_tile_order) marches a few
+// probe rays per tile and orders the tiles by their estimated work, heaviest
+// first; the served kernel (k_render_served) runs the same per-tile code on
+// requests of several scenes described in device memory.
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 #include <hip/hip_bf16.h>
