@@ -286,6 +286,18 @@ def test_tile_order_many_frames_in_flight(torch, merf, full_scene):
         r.close()
 
 
+def test_tile_order_effort_key_boundary(torch, merf, full_scene):
+    say("full scene at 2048x2048 (65536 tiles: probe rays evaluate samples) and 2048x2056 (65792 tiles: "
+        "probe rays stop at the first occupied sample), both against the plain order")
+    pose = synth.full_camera().c2w[0].astype(np.float64)
+    for w, h in ((2048, 2048), (2048, 2056)):
+        cams = synth.make_cameras([pose], [(w, h)])
+        a = gpu_render(torch, merf, full_scene, cams)
+        b = gpu_render(torch, merf, full_scene, cams, order="plain")
+        assert np.array_equal(a, b), (w, h)
+        assert a[:, 3].max() > 0.5
+
+
 def test_tile_order_4k_frame(torch, merf, full_scene):
     say("full scene, one 3840x2160 view (129600 tiles, the largest ordered launch size range)")
     cams = synth.make_cameras([synth.full_camera().c2w[0].astype(np.float64)], [(3840, 2160)])
