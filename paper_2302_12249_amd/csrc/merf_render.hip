@@ -1165,15 +1165,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 // smallest that gives every tile a workgroup of its own; workgroups past the
 // launch's tiles exit at once.  A launch larger than the largest such class
 // is persistent (a grid of the device's wave slots): its workgroups go on
-// taking positions from the XCD's
-// counter, asking for the next one as they start each tile so that the
-// atomic's round trip overlaps the render, until the share is exhausted; the
-// counters are zeroed before such a launch (k_zero_ctl).  (A 4096-workgroup
-// persistent grid rendered a 1080p request 13% slower than one workgroup per
-// tile, and 5% slower once its workgroups no longer counted themselves out
-// on one shared counter at the end.)  Each tile belongs to one request, which
-// names its camera, march parameters and scene (a slot of the server's scene
-// table).
+// taking positions from the XCD's counter, asking for the next one as they
+// start each tile so that the atomic's round trip overlaps the render, until
+// the share is exhausted; the counters are zeroed before such a launch
+// (k_zero_ctl).  (A 4096-workgroup persistent grid rendered a 1080p request
+// 13% slower than one workgroup per tile, and 5% slower once its workgroups
+// no longer counted themselves out on one shared counter at the end.)  Each
+// tile belongs to one request, which names its camera, march parameters and
+// scene (a slot of the server's scene table).
 typedef const __attribute__((address_space(4))) DevScene ConstScene;
 typedef const __attribute__((address_space(4))) ServeLaunch ConstLaunch;
 typedef const __attribute__((address_space(4))) ServeWork ConstWork;

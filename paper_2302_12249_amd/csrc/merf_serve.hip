@@ -158,7 +158,7 @@ hipError_t launch_slot(merf_server *S, Slot &sl, const merf_render_params &p, in
     const int grid = grid_of_class(gclass);
     auto enqueue = [&]() {
         hipError_t e = hipMemcpyAsync(sl.desc_dev, sl.staging, sizeof(ServeLaunch), hipMemcpyHostToDevice, sl.stream);
-        // only a launch of the largest class can take positions from the counters
+        // only a launch of the persistent class takes positions from the counters
         if (e == hipSuccess && gclass == kGridClasses - 1) e = launch_zero_ctl(sl.ctl_dev, sl.stream);
         if (e == hipSuccess)
             e = launch_render_served(S->table_dev, sl.desc_dev, sl.ctl_dev, p.mlp_prec, p.feat_prec, p.skip_mode, grid,
