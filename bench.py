@@ -627,7 +627,8 @@ def main():
     ap.add_argument("--workload", choices=["full", "precision", "stress", "variants", "resolutions"], default="full",
                     help="full (default, the headline line), precision (16 x 1080p views), stress, "
                          "variants (representations: memory against speed) or resolutions (tile order by frame size)")
-    ap.add_argument("--stress-scenes", type=int, default=32)
+    ap.add_argument("--stress-scenes", type=int, default=32,
+                    help="resident scenes of the Stress config (in the default line and --workload stress; 0: skip)")
     ap.add_argument("--precision-steps", type=int, default=5,
                     help="timed calls per mode of the 16 x 1080p precision config in the default line (0 skips it)")
     ap.add_argument("--serve-requests", type=int, default=240,
@@ -833,6 +834,13 @@ def main():
         del src, dst
     if args.serve_requests > 0:
         res["served"] = serving_leg(args.serve_requests)
+    if args.serve_requests > 0 and args.stress_scenes > 0 and not args.headline_only:
+        # the Stress config: many resident scenes, 4K and 512^2 requests, bf16
+        # MLP through the server, beside plain fp32 calls
+        st = stress_workload(args.stress_scenes, args.serve_requests)
+        res["stress"] = {"workload": st["config"]["workload"], "resident_bytes": st["config"]["resident_bytes"],
+                         "served_Mrays/s": st["value"], "served": st["served"],
+                         "plain_fp32_Mrays/s": st["plain_fp32_Mrays/s"]}
     images = {"f32": out.cpu().numpy()}
     for name, v in prec.items():
         images[name] = v.pop("_img").cpu().numpy()
