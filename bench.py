@@ -142,8 +142,10 @@ def cpu_baseline(scene, cams, seconds: float):
     import numpy as np
     rows = np.arange(stride // 2, H, stride)
     sel = (rows[:, None] * W + np.arange(W)[None, :]).reshape(-1)
-    return ({"value": n / dt / 1e6, "unit": "Mrays/s", "cores": oracle.max_threads(), "kind": "oracle",
-             "sample": f"every {stride}th row of the {W}x{H} frame ({n} rays, {dt:.1f} s, FP64 C, OpenMP)",
+    threads = oracle.max_threads()
+    return ({"value": n / dt / 1e6, "unit": "Mrays/s", "cores": threads, "kind": "oracle",
+             "sample": (f"one row in {stride} of" if stride > 1 else "all rows of") +
+                       f" the {W}x{H} frame ({n} rays, {dt:.1f} s on {threads} threads, FP64 C, OpenMP)",
              "one_thread_Mrays/s": one.shape[0] / dt1 / 1e6,
              "one_thread_sample": f"every 135th row ({one.shape[0]} rays, {dt1:.1f} s)",
              "cpu_model": cpu_model()},
