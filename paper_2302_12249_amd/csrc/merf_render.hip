@@ -917,6 +917,10 @@ __device__ __forceinline__ void render_tile(const S &sc, const Cam &cam, int lt,
     // march gives.
     float4 *pq = reinterpret_cast<float4 *>(lds);             // [kQueue][64] parked (p, delta)
     float4 *rs = pq + kQueue * 64;                            // [64] x 2: results by shading slot
+    // finite from the start: the branch-free compositing reads slot 0 for
+    // lanes with nothing to composite
+    rs[2 * lane] = make_float4(1.0f, 0.0f, 0.0f, 0.0f);
+    rs[2 * lane + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     int *imap = reinterpret_cast<int *>(rs + 2 * 64);          // [64] shading slot -> parked entry
     int pc = 0;                                               // samples parked by this lane
     while (__any(alive || pc > 0)) {
@@ -1071,7 +1075,30 @@ __device__ __forceinline__ void render_tile(const S &sc, const Cam &cam, int lt,
         for (int j = 0; j < kQueue; ++j) {
             const int item = before + lanes_below(__ballot(pc > j));
             before += __popcll(__ballot(pc > j));
-            if (j < pc && item < 64 && !terminated) {
+            if constexpr (!kStats) {
+                // branch-free: an unused slot reads the result area at item 0
+                // (always finite) and contributes with weight 0, which leaves
+                // every accumulator bit for bit unchanged (the branch around
+                // the update made the compiler copy the accumulators)
+                const bool use = j < pc && item < 64 && !terminated;
+                const int it = use ? item : 0;
+                const float4 ra = rs[2 * it], rbv = rs[2 * it + 1];
+                const float alpha = use ? 1.0f - ra.x : 0.0f;
+                const float wt = acc.T * alpha;
+                acc.cd0 = fmaf(wt, ra.y, acc.cd0);
+                acc.cd1 = fmaf(wt, ra.z, acc.cd1);
+                acc.cd2 = fmaf(wt, ra.w, acc.cd2);
+                acc.f0 = fmaf(wt, rbv.x, acc.f0);
+                acc.f1 = fmaf(wt, rbv.y, acc.f1);
+                acc.f2 = fmaf(wt, rbv.z, acc.f2);
+                acc.f3 = fmaf(wt, rbv.w, acc.f3);
+                acc.T *= use ? ra.x : 1.0f;
+                done += use ? 1 : 0;
+                if (use && acc.T < tp.t_min) {   // early termination (Sec. 6)
+                    alive = false;
+                    terminated = true;
+                }
+            } else if (j < pc && item < 64 && !terminated) {
                 const int e = j * 64 + lane;
                 if (kStats && ma.rec) {
                     // measurement: record the texel offsets of this sample
