@@ -365,6 +365,10 @@ def test_fp16_features_full_sampled(torch, merf, full_scene, feat):
     gpu = gpu_render(torch, merf, full_scene, cams, feat_prec=feat, mlp_prec="f16")
     ref, st = oracle.render(full_scene, cams, rows_stride=54, row_offset=7)
     check(gpu[rows_of(cams, 54, 7)], ref, st["fragile"], f"full feat {feat} mlp f16", min_psnr=MIN_PSNR_DB)
+    if feat == "f16_interp":
+        # density is summed in fp32 as in the fp32 path: the same alpha bit for bit
+        f32 = gpu_render(torch, merf, full_scene, cams, mlp_prec="f16")
+        assert np.array_equal(gpu[:, 3], f32[:, 3])
 
 
 def test_precision_orbit_views_sampled(torch, merf, full_scene):
