@@ -196,7 +196,10 @@ int merf_render_noalloc(merf_scene_t s, const merf_camera *cams, int32_t n_cams,
                         float *out_rgba_dev, void *hip_stream);
 
 /*
- * Release a scene.  Waits for all work queued on the device before freeing.
+ * Release a scene.  Waits for all work queued on the device before freeing
+ * (renders that read the scene may be queued on any stream, and hipFree
+ * waits for the device in any case); the serving runtime (merf_serve.h)
+ * releases its scenes stream-ordered instead, without blocking.
  * Errors: MERF_E_INVALID for NULL, an unknown handle or a second free.
  */
 int merf_free(merf_scene_t s);
