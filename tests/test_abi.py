@@ -158,6 +158,21 @@ def test_budget_rejects_before_allocating():
         merf.set_hbm_budget(2 ** 63)
 
 
+def test_render_params_precision_names():
+    """The binding's precision names map to the codes include/merf.h states:
+    mlp_prec 0 / 1 / 2 = fp32 / fp16 / bf16; feat_prec 0 = fp32
+    interpolation, 1 = codes dequantised to float16 first, 2 = appearance
+    interpolated from float16 operands."""
+    for mlp, code in (("f32", 0), ("f16", 1), ("bf16", 2)):
+        assert merf.render_params(mlp_prec=mlp).mlp_prec == code
+    for feat, code in (("f32", 0), ("f16", 1), ("f16_interp", 2)):
+        assert merf.render_params(feat_prec=feat).feat_prec == code
+    p = merf.render_params(mlp_prec=1, feat_prec=2, skip="levels", order="plain")
+    assert (p.mlp_prec, p.feat_prec, p.skip_mode, p.tile_order) == (1, 2, 1, 1)
+    with pytest.raises(KeyError):
+        merf.render_params(feat_prec="bf16")      # no bfloat16 feature mode
+
+
 def test_bad_handles():
     lib = merf.load()
     assert lib.merf_free(None) == merf.MERF_E_INVALID
