@@ -296,6 +296,36 @@ def test_launch_beyond_largest_class_is_persistent(torch, merf):
         srv.close()
 
 
+def test_launch_class_boundary(torch, merf):
+    """262144 tiles (4096x4096) is the largest launch with a workgroup per
+    tile; 262656 tiles (4096x4104) takes the persistent grid.  Each request
+    bitwise as rendered alone."""
+    say("serving: launches of 262144 tiles (one workgroup per tile) and 262656 tiles (persistent grid)")
+    scene = synth.preset_scene("tiny", seed=6)
+    sizes = [(4096, 4096), (4096, 4104)]
+    cams = synth.random_cameras(len(sizes), seed=31, sizes=sizes, inside=2.5)
+    arr = merf.camera_array(cams)
+    srv = merf.Server(slots=1, max_batch=1, use_graphs=True)
+    try:
+        sid = srv.add_scene(scene)
+        outs = [torch.full((w * h, 4), float("nan"), device="cuda") for w, h in sizes]
+        torch.cuda.synchronize()
+        tickets = [srv.submit(sid, arr, i, outs[i].data_ptr(), merf.render_params()) for i in range(len(sizes))]
+        for t in tickets:
+            srv.wait(t)
+        assert srv.stats()["launches"] == 2
+        r = merf.Renderer(scene)
+        try:
+            for i in range(len(sizes)):
+                alone = r.render(cams.subset(i))
+                torch.cuda.synchronize()
+                assert torch.equal(outs[i], alone), i
+        finally:
+            r.close()
+    finally:
+        srv.close()
+
+
 def test_busy_scene_cannot_be_removed(torch, merf, scenes):
     say("serving: removing a scene with queued work is refused")
     srv = merf.Server(slots=1, max_batch=1)
