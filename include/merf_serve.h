@@ -11,12 +11,18 @@
  *    every registered scene.  A scene is made resident at registration if it
  *    fits the device-memory budget, otherwise when a request needs it.  The
  *    oldest waiting request whose scene is not resident gets it loaded as
- *    soon as the budget allows; with evict_idle, room is made by evicting,
- *    least recently used first, resident scenes that no older request needs
- *    (a scene still rendering is first drained: it takes no newer requests
- *    until it is evicted).  Requests older than the waiting one keep being
+ *    soon as the budget allows; with evict_idle, room is made by evicting
+ *    resident scenes that no older request needs, least requested first
+ *    (request counts decayed with a 2 s time constant; ties: least recently
+ *    used), so that under a skewed popularity the rarely requested scenes
+ *    take turns in the memory the popular ones leave (a scene still
+ *    rendering is first drained: it takes no newer requests until it is
+ *    evicted).  Requests older than the waiting one keep being
  *    served, so every request is eventually admitted.  Without evict_idle,
- *    only merf_server_remove_scene frees memory.
+ *    only merf_server_remove_scene frees memory.  After a scene's first
+ *    upload, the server's host copy is the device image that upload built
+ *    (packed bricks, empty-space grids and all), so a re-admission is a
+ *    single host-to-device copy and runs no kernels beside the renders.
  *  - Continuous batching: requests queue on the host.  A worker thread owns
  *    `slots` HIP streams.  Whenever a slot is free, it fuses the oldest
  *    request whose scene is resident with the following such requests that
@@ -31,9 +37,10 @@
  *    persistent: 4096 workgroups go on taking tiles from a device-side
  *    counter per XCD until the launch's tiles are done.  It reads its work
  *    descriptors (per request: scene slot, camera, output, march parameters)
- *    and a device table of the resident scenes from device memory.  With use_graphs, each slot captures one
- *    hipGraph per kernel variant and grid size -- a copy of the descriptors
- *    into device memory, then the kernel -- and replays it unchanged.
+ *    and a device table of the resident scenes from device memory.  With
+ *    use_graphs, each slot captures one hipGraph per kernel variant and grid
+ *    size -- a copy of the descriptors into device memory, then the kernel --
+ *    and replays it unchanged.
  *
  * Every pixel of a request is computed exactly as merf_render computes it
  * (same per-tile code, same arguments per camera), so a result does not
@@ -59,7 +66,7 @@ typedef struct {
     int32_t slots;               /* launches in flight at once, 1..8 (one HIP stream each) */
     int32_t max_batch;           /* requests fused into one launch, 1..16 */
     int32_t use_graphs;          /* 1: replay captured hipGraphs; 0: plain launches */
-    int32_t evict_idle;          /* 1: evict idle scenes (LRU) to admit a new one */
+    int32_t evict_idle;          /* 1: evict idle scenes (least requested first) to admit a new one */
     int32_t pad;
     size_t hbm_budget;           /* device bytes for resident scenes; 0 = no cap */
 } merf_server_config;
@@ -73,6 +80,7 @@ typedef struct {
     uint64_t evictions;          /* scenes evicted to admit others */
     uint64_t admissions;         /* scenes made resident (at registration or for a request) */
     uint64_t admission_us;       /* host time spent making them resident (upload to table entry) */
+    uint64_t image_admissions;   /* of the admissions, those copied from a kept device image */
     size_t resident_bytes;       /* device bytes of resident scenes */
     int32_t resident_scenes;
     int32_t registered;          /* registered scenes, resident or not */

@@ -598,6 +598,72 @@ int scene_upload_on(const merf_scene_desc *desc, hipStream_t stream, merf_scene_
     return upload_impl(desc, out, true, stream);
 }
 
+int scene_image_on(merf_scene_t s, void *host, size_t host_bytes, hipStream_t stream, SceneImage *img) {
+    clear_error();
+    if (!live(s)) return fail(MERF_E_INVALID, "scene_image_on: invalid scene handle");
+    if (!img || !host || host_bytes < s->dev_bytes)
+        return fail(MERF_E_INVALID, "scene_image_on: the image needs %zu host bytes", s->dev_bytes);
+    hipError_t e = hipMemcpyAsync(host, s->dev_base, s->dev_bytes, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "scene image");
+    img->ds = s->ds;
+    img->base = reinterpret_cast<uintptr_t>(s->dev_base);
+    img->bytes = s->dev_bytes;
+    img->nbricks = s->nbricks;
+    return MERF_OK;
+}
+
+int scene_from_image_on(const SceneImage &img, const void *host, hipStream_t stream, merf_scene_t *out) {
+    clear_error();
+    if (!out) return fail(MERF_E_INVALID, "output handle pointer is NULL");
+    *out = nullptr;
+    if (!host || img.bytes == 0) return fail(MERF_E_INVALID, "scene_from_image_on: empty image");
+    {
+        std::lock_guard<std::mutex> lk(g_mutex);
+        if (g_in_use + img.bytes > g_budget)
+            return fail(MERF_E_OOM, "scene needs %zu device bytes; %zu in use, budget %zu", img.bytes, g_in_use, g_budget);
+        g_in_use += img.bytes;
+    }
+    void *base = nullptr;
+    hipError_t e = hipMallocAsync(&base, img.bytes, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(base, host, img.bytes, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess || !base) {
+        (void)hipGetLastError();
+        if (base) {
+            (void)hipFreeAsync(base, stream);
+            (void)hipStreamSynchronize(stream);
+        }
+        std::lock_guard<std::mutex> lk(g_mutex);
+        g_in_use -= img.bytes;
+        return fail(MERF_E_OOM, "scene image of %zu bytes: %s", img.bytes, hipGetErrorString(e));
+    }
+    // every array keeps its offset in the allocation
+    auto at = [&](const void *p) -> const uint8_t * {
+        return p ? static_cast<const uint8_t *>(base) + (reinterpret_cast<uintptr_t>(p) - img.base) : nullptr;
+    };
+    merf_scene *s = new merf_scene();
+    s->magic = kMagic;
+    s->dev_base = base;
+    s->dev_bytes = img.bytes;
+    s->nbricks = img.nbricks;
+    s->ordered = true;
+    DevScene &ds = s->ds;
+    ds = img.ds;
+    ds.brick_index = reinterpret_cast<const int32_t *>(at(img.ds.brick_index));
+    ds.bricks = at(img.ds.bricks);
+    ds.planes = at(img.ds.planes);
+    for (int l = 0; l < kMaxLevels; ++l) ds.occ[l] = at(img.ds.occ[l]);
+    ds.dist = at(img.ds.dist);
+    ds.mlp = reinterpret_cast<const float *>(at(img.ds.mlp));
+    {
+        std::lock_guard<std::mutex> lk(g_mutex);
+        g_live.insert(s);
+    }
+    *out = s;
+    return MERF_OK;
+}
+
 int scene_release_on(merf_scene_t s, hipStream_t stream) {
     clear_error();
     if (!unregister(s)) return fail(MERF_E_INVALID, "scene_release_on: unknown or already freed scene handle");

@@ -30,6 +30,26 @@ int scene_upload_on(const merf_scene_desc *desc, hipStream_t stream, merf_scene_
 // running work reads it.
 int scene_release_on(merf_scene_t s, hipStream_t stream);
 
+// A scene's device image: the bytes of its device allocation once an upload
+// has built it (packed bricks, occupancy levels, empty-space grids, planes,
+// MLP) and its device view at the address it was taken from.  The arrays keep
+// their offsets in the allocation, so the image restored at another address
+// renders bit for bit as the scene it was taken from, with no build step.
+struct SceneImage {
+    DevScene ds;                 // device view at `base`
+    uintptr_t base = 0;          // device address the image was taken from
+    size_t bytes = 0;
+    int32_t nbricks = 0;
+};
+// Copy live scene s's device bytes into host[0, host_bytes) in order on
+// `stream` (pinned host memory makes it a plain DMA) and describe them in
+// img; returns once the copy is done.
+int scene_image_on(merf_scene_t s, void *host, size_t host_bytes, hipStream_t stream, SceneImage *img);
+// A scene made resident from an image: one stream-ordered allocation and one
+// host-to-device copy on `stream`, no kernels; returns once resident.  Counts
+// against the device budget like an upload.
+int scene_from_image_on(const SceneImage &img, const void *host, hipStream_t stream, merf_scene_t *out);
+
 // Device view of a live scene handle, or nullptr.
 const DevScene *scene_dev(merf_scene_t s);
 

@@ -2,8 +2,10 @@
 //
 // Registered scenes (host copies owned by the server) become resident in
 // device memory under a byte budget: at registration when they fit, otherwise
-// when a request needs them, evicting the least recently used scenes that no
-// earlier request needs.  A worker thread continuously batches waiting
+// when a request needs them, evicting the least requested scenes that no
+// earlier request needs.  After a scene's first upload its host copy is the
+// device image that upload built, so a re-admission is one copy and runs no
+// kernels beside the renders.  A worker thread continuously batches waiting
 // requests of resident scenes -- any scenes, any image sizes -- into
 // launches of the served render kernel on several HIP streams, with a grid
 // from a fixed set of classes (persistent beyond the largest); a launch reads
@@ -15,6 +17,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstdlib>
 #include <cstring>
@@ -42,6 +45,8 @@ constexpr int kVariants = 18;                // MLP fp32 / fp16 / bf16  x  featu
 // four waves per SIMD) for larger launches.
 constexpr int kGridClasses = 8;
 constexpr int kPersistentGrid = 4096;
+// time constant (seconds) of the decayed request counts that order evictions
+constexpr double kHeatTau = 2.0;
 
 enum SceneState { kAbsent = 0, kLoading, kResident };
 
@@ -60,15 +65,23 @@ struct Request {
 // A registered scene: the server's host copy of the baked scene, and its
 // residency.
 struct SceneEntry {
-    void *host = nullptr;                    // one buffer with all arrays: pinned, else pageable
+    // one host buffer, pinned if possible: the registered arrays (desc points
+    // into it) until the first upload, then the device image that upload built
+    void *host = nullptr;
     bool pinned = false;
-    merf_scene_desc desc{};                  // points into host
+    bool imaged = false;                     // host holds img's bytes
+    merf_scene_desc desc{};                  // points into host while !imaged
+    SceneImage img{};
     size_t need = 0;                         // device bytes of a resident copy
     int res = 1;                             // max(L, R): default step 4/res
     SceneState state = kAbsent;
     merf_scene_t h = nullptr;
     int slot = -1;                           // scene table slot while resident
     uint64_t last_used = 0;
+    // requests for the scene, each decaying with time constant kHeatTau since
+    // its submission (value at heat_t): the eviction order, coldest first
+    double heat = 0.0;
+    Clock::time_point heat_t{};
     int queued = 0, running = 0;
     bool draining = false;                   // being emptied to make room (see loader_main)
 };
@@ -331,12 +344,49 @@ int free_table_slot(merf_server *S) {
     return -1;
 }
 
-// Make scene se resident: upload it and fill its table slot (caller holds
-// load_mu, not mu; se->state is kLoading and its bytes are reserved).
+void free_host(SceneEntry &e);
+
+// After a scene's first upload, the server's host copy of its arrays is
+// replaced by the device image that upload built.  Later admissions are then
+// one host-to-device copy, which runs on a copy engine: the build kernels
+// (brick packing, empty-space grids) would otherwise run again on every
+// re-admission, beside the renders of the resident scenes, and slow them.
+// Best effort: without host memory for the image, the arrays stay and every
+// admission builds the scene again.
+void keep_image(merf_server *S, SceneEntry &e, merf_scene_t h) {
+    const size_t n = e.need;
+    void *buf = nullptr;
+    const bool pinned = hipHostMalloc(&buf, n, hipHostMallocDefault) == hipSuccess && buf;
+    if (!pinned) {
+        (void)hipGetLastError();
+        buf = std::malloc(n);
+        if (!buf) return;
+    }
+    SceneImage img;
+    if (scene_image_on(h, buf, n, S->load_stream, &img) != MERF_OK) {
+        if (pinned) (void)hipHostFree(buf);
+        else std::free(buf);
+        clear_error();
+        return;
+    }
+    free_host(e);
+    e.host = buf;
+    e.pinned = pinned;
+    e.imaged = true;
+    e.img = img;
+    e.desc = merf_scene_desc{};
+}
+
+// Make scene se resident: upload it (from its device image once there is
+// one) and fill its table slot (caller holds load_mu, not mu; se->state is
+// kLoading and its bytes are reserved).
 int admit(merf_server *S, SceneEntry *se, int slot) {
     const auto t0 = Clock::now();
     merf_scene_t h = nullptr;
-    int rc = scene_upload_on(&se->desc, S->load_stream, &h);
+    const bool from_image = se->imaged;
+    int rc = from_image ? scene_from_image_on(se->img, se->host, S->load_stream, &h)
+                        : scene_upload_on(&se->desc, S->load_stream, &h);
+    if (rc == MERF_OK && !se->imaged) keep_image(S, *se, h);
     if (rc == MERF_OK) rc = write_table(S, slot, h);
     const auto us = std::chrono::duration_cast<std::chrono::microseconds>(Clock::now() - t0).count();
     std::lock_guard<std::mutex> lk(S->mu);
@@ -353,6 +403,7 @@ int admit(merf_server *S, SceneEntry *se, int slot) {
     se->state = kResident;
     se->last_used = ++S->tick;
     ++S->st.admissions;
+    if (from_image) ++S->st.image_admissions;
     return MERF_OK;
 }
 
@@ -397,12 +448,20 @@ void fail_queued(merf_server *S, int32_t id, int status) {
     }
 }
 
+double heat_at(const SceneEntry &e, Clock::time_point now) {
+    const double dt = std::chrono::duration<double>(now - e.heat_t).count();
+    return e.heat * std::exp(-std::max(dt, 0.0) / kHeatTau);
+}
+
 // Admission by memory.  The oldest waiting request whose scene is absent
 // gets its scene loaded as soon as the budget allows.  Room is made by
-// evicting, least recently used first, resident scenes that no request older
-// than it needs; those still running are first drained: they take no newer
-// requests until they are evicted.  Requests older than the waiting one keep
-// being served, so every request is eventually admitted.
+// evicting resident scenes that no request older than it needs, least
+// requested first (request counts decayed over kHeatTau seconds, then least
+// recently used): with a skewed popularity, the tail of rarely requested
+// scenes takes turns in the memory left over while the popular ones stay.
+// Victims still running are first drained: they take no newer requests until
+// they are evicted.  Requests older than the waiting one keep being served,
+// so every request is eventually admitted.
 void loader_main(merf_server *S) {
     (void)hipSetDevice(S->device);
     std::unique_lock<std::mutex> lk(S->mu);
@@ -461,8 +520,13 @@ void loader_main(merf_server *S) {
                 }
                 if (!needed) cand.push_back(&e);
             }
-            std::sort(cand.begin(), cand.end(),
-                      [](const SceneEntry *a, const SceneEntry *b) { return a->last_used < b->last_used; });
+            const auto now = Clock::now();
+            std::vector<std::pair<double, SceneEntry *>> order;
+            for (SceneEntry *e : cand) order.emplace_back(heat_at(*e, now), e);
+            std::sort(order.begin(), order.end(), [](const auto &a, const auto &b) {
+                return a.first != b.first ? a.first < b.first : a.second->last_used < b.second->last_used;
+            });
+            for (size_t i = 0; i < order.size(); ++i) cand[i] = order[i].second;
             size_t room = S->budget - std::min(S->budget, S->resident);
             bool slot_ok = slot >= 0;
             std::vector<SceneEntry *> victims;
@@ -509,6 +573,7 @@ void free_host(SceneEntry &e) {
     if (e.pinned) (void)hipHostFree(e.host);
     else std::free(e.host);
     e.host = nullptr;
+    e.imaged = false;
 }
 
 // The server's host copy of a scene descriptor's arrays, in one buffer:
@@ -748,6 +813,8 @@ int merf_server_submit(merf_server_t S, int32_t scene_id, const merf_camera *cam
         S->reqs.emplace(t, r);
         S->queue.push_back(t);
         ++it->second.queued;
+        it->second.heat = heat_at(it->second, r.t_submit) + 1.0;
+        it->second.heat_t = r.t_submit;
         ++S->st.submitted;
         absent = it->second.state == kAbsent;
         ++S->epoch;

@@ -305,7 +305,7 @@ class merf_server_config(C.Structure):
 class merf_server_stats(C.Structure):
     _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("launches", C.c_uint64),
                 ("graph_launches", C.c_uint64), ("mixed_launches", C.c_uint64), ("evictions", C.c_uint64),
-                ("admissions", C.c_uint64), ("admission_us", C.c_uint64),
+                ("admissions", C.c_uint64), ("admission_us", C.c_uint64), ("image_admissions", C.c_uint64),
                 ("resident_bytes", C.c_size_t), ("resident_scenes", C.c_int32), ("registered", C.c_int32),
                 ("max_inflight", C.c_int32), ("pad", C.c_int32)]
 

@@ -2,7 +2,7 @@
 batching of uneven requests over several scenes, fused into persistent
 launches across scenes, must give every request exactly the image
 merf_render gives it alone; scenes are admitted by the device-memory budget,
-evicted least recently used first and re-admitted on demand."""
+evicted least requested first and re-admitted on demand."""
 import threading
 import time
 
@@ -188,12 +188,13 @@ def test_admission_by_budget_and_eviction(torch, merf, scenes):
         srv.wait(t)
         st = srv.stats()
         assert st["resident_scenes"] == 2 and st["admissions"] == 3 and st["evictions"] == 0
+        assert st["image_admissions"] == 0                 # every scene's first upload builds it
         alone = render_alone(torch, merf, scenes[2], cams, 0, "f32")
         assert np.array_equal(out.cpu().numpy(), alone)
     finally:
         srv.close()
     # with eviction: requests cycling over three scenes that do not fit
-    # together; scenes are evicted least recently used first and re-admitted
+    # together; scenes are evicted and re-admitted
     srv = merf.Server(slots=2, max_batch=4, hbm_budget=budget, evict_idle=True)
     try:
         ids = [srv.add_scene(s) for s in scenes]
@@ -208,11 +209,47 @@ def test_admission_by_budget_and_eviction(torch, merf, scenes):
         for t in ts:
             srv.wait(t)
         st = srv.stats()
-        say(f"  launches {st['launches']}, admissions {st['admissions']}, evictions {st['evictions']}")
+        say(f"  launches {st['launches']}, admissions {st['admissions']} ({st['image_admissions']} from "
+            f"device images), evictions {st['evictions']}")
         assert st["completed"] == n and st["evictions"] >= 1 and st["admissions"] == 2 + st["evictions"]
+        # the first admission of each scene builds it; every later one copies
+        # the device image kept from that build
+        assert st["image_admissions"] == st["admissions"] - 3
         assert st["resident_bytes"] <= budget and st["resident_scenes"] <= 2
         for i in range(n):
             alone = render_alone(torch, merf, scenes[order[i]], cams, i, "f32")
+            assert np.array_equal(outs[i].cpu().numpy(), alone), i
+    finally:
+        srv.close()
+
+
+def test_eviction_keeps_the_most_requested_scene(torch, merf, scenes):
+    """Of two resident scenes, the one with more recent requests stays when a
+    third needs room, even if the other was used last."""
+    say("serving: eviction order by request counts")
+    probe = merf.Server(slots=1)
+    probe.add_scene(scenes[0])
+    one = probe.stats()["resident_bytes"]
+    probe.close()
+    srv = merf.Server(slots=2, max_batch=4, hbm_budget=2 * one + one // 2, evict_idle=True)
+    try:
+        a, b, c = [srv.add_scene(s) for s in scenes]
+        assert srv.stats()["resident_scenes"] == 2             # a and b
+        order = [a] * 8 + [b] + [c] + [a]
+        cams = synth.random_cameras(len(order), seed=23, sizes=[(40, 32)] * len(order), inside=2.5)
+        arr = merf.camera_array(cams)
+        outs = [torch.full((40 * 32, 4), float("nan"), device="cuda") for _ in order]
+        torch.cuda.synchronize()
+        for i, sid in enumerate(order):                       # one at a time: b is used after a
+            srv.wait(srv.submit(sid, arr, i, outs[i].data_ptr(), merf.render_params()))
+            if i == 9:
+                st = srv.stats()
+                assert st["admissions"] == 3 and st["evictions"] == 1
+        st = srv.stats()
+        say(f"  admissions {st['admissions']}, evictions {st['evictions']}")
+        assert st["admissions"] == 3 and st["evictions"] == 1     # a stayed: b made room for c
+        for i, sid in enumerate(order):
+            alone = render_alone(torch, merf, scenes[[a, b, c].index(sid)], cams, i, "f32")
             assert np.array_equal(outs[i].cpu().numpy(), alone), i
     finally:
         srv.close()
@@ -255,6 +292,7 @@ def test_admission_while_serving_from_threads(torch, merf, scenes):
         say(f"  launches {st['launches']} (mixed-scene {st['mixed_launches']}), admissions {st['admissions']}, "
             f"evictions {st['evictions']}")
         assert st["completed"] == n and st["evictions"] >= 1
+        assert st["image_admissions"] == st["admissions"] - 4
         for i in range(n):
             alone = render_alone(torch, merf, four[which[i]], cams, i, "f32")
             assert np.array_equal(outs[i].cpu().numpy(), alone), i
