@@ -152,6 +152,45 @@ def cpu_baseline(scene, cams, seconds: float):
             (out, sel))
 
 
+def _serving_mix(n_requests: int, seed: int):
+    """The serving mix's requests: 8 scenes, resolutions uniform over four
+    sizes, scenes drawn from a Zipf(1.5) popularity.  Returns the scenes, the
+    four sizes, each request's size, the cameras, each request's scene and the
+    generator (for the arrival times drawn after it)."""
+    import numpy as np
+    import synth
+
+    scenes = synth.serving_scenes()
+    sizes_all = [(256, 256), (512, 512), (1280, 720), (1920, 1080)]
+    rng = np.random.default_rng(seed)
+    sizes = [sizes_all[i] for i in rng.integers(0, len(sizes_all), n_requests)]
+    cams = synth.random_cameras(n_requests, seed=seed + 1, sizes=sizes)
+    pop = 1.0 / np.arange(1, len(scenes) + 1) ** 1.5
+    scene_of = rng.choice(len(scenes), n_requests, p=pop / pop.sum())
+    return scenes, sizes_all, sizes, cams, scene_of, rng
+
+
+def _open_loop_served(srv, ids, scene_of, arr, outs, params, arrive):
+    """Submit request i to the server at arrive[i] seconds after the start,
+    then wait for all.  Returns each request's (latency ms, queue ms) and the
+    seconds from the start to the last completion.  The latency counts from
+    the scheduled arrival: the server's own figure (from its submit to the
+    completion) plus how late the submit call returned, so that a client
+    loop that falls behind its schedule cannot hide waiting."""
+    import numpy as np
+
+    tk, late = [], np.zeros(len(arrive))
+    t0 = time.perf_counter()
+    for i in range(len(arrive)):
+        while time.perf_counter() - t0 < arrive[i]:
+            pass
+        tk.append(srv.submit(ids[scene_of[i]], arr, i, outs[i].data_ptr(), params))
+        late[i] = time.perf_counter() - t0 - arrive[i]
+    waited = [srv.wait(t) for t in tk]
+    span = time.perf_counter() - t0
+    return [(w[0] + 1e3 * d, w[1]) for w, d in zip(waited, late)], span
+
+
 def _open_loop_plain(renderers, arr, scene_of, sizes, arrive, params):
     """The plain path on a request stream: each request is one merf_render
     call on one stream, issued at its arrival time, followed by a timing
@@ -204,16 +243,9 @@ def serving_leg(n_requests: int, seed: int = 200, budget: int = 1 << 30):
     import numpy as np
     import torch
     import oracle
-    import synth
     from paper_2302_12249_amd import merf
 
-    scenes = synth.serving_scenes()
-    sizes_all = [(256, 256), (512, 512), (1280, 720), (1920, 1080)]
-    rng = np.random.default_rng(seed)
-    sizes = [sizes_all[i] for i in rng.integers(0, len(sizes_all), n_requests)]
-    cams = synth.random_cameras(n_requests, seed=seed + 1, sizes=sizes)
-    pop = 1.0 / np.arange(1, len(scenes) + 1) ** 1.5
-    scene_of = rng.choice(len(scenes), n_requests, p=pop / pop.sum())
+    scenes, sizes_all, sizes, cams, scene_of, rng = _serving_mix(n_requests, seed)
     arr = merf.camera_array(cams)
     p16 = merf.render_params(mlp_prec="f16")
     rays = sum(w * h for (w, h) in sizes)
@@ -241,14 +273,7 @@ def serving_leg(n_requests: int, seed: int = 200, budget: int = 1 << 30):
         lam = 0.7 * capacity
         arrive = np.cumsum(rng.exponential(1.0 / lam, n_requests))
         st1 = srv.stats()
-        tk = []
-        t0 = time.perf_counter()
-        for i in range(n_requests):
-            while time.perf_counter() - t0 < arrive[i]:
-                pass
-            tk.append(srv.submit(ids[scene_of[i]], arr, i, outs[i].data_ptr(), p16))
-        waited = [srv.wait(t) for t in tk]
-        span = time.perf_counter() - t0
+        waited, span = _open_loop_served(srv, ids, scene_of, arr, outs, p16, arrive)
         lat = np.array([w[0] for w in waited])
         st = srv.stats()
     finally:
@@ -295,13 +320,8 @@ def serving_leg(n_requests: int, seed: int = 200, budget: int = 1 << 30):
         torch.cuda.synchronize()
         for t in [srv.submit(ids[scene_of[i]], arr, i, outs[i].data_ptr(), p16) for i in range(min(32, n_requests))]:
             srv.wait(t)
-        tk = []
-        t0 = time.perf_counter()
-        for i in range(n_requests):
-            while time.perf_counter() - t0 < arrive[i]:
-                pass
-            tk.append(srv.submit(ids[scene_of[i]], arr, i, outs[i].data_ptr(), p16))
-        lat_all = np.array([srv.wait(t)[0] for t in tk])
+        waited, _ = _open_loop_served(srv, ids, scene_of, arr, outs, p16, arrive)
+        lat_all = np.array([w[0] for w in waited])
     finally:
         srv.close()
     res["served_all_resident_same_stream"] = {"p50_ms": float(np.percentile(lat_all, 50)),
@@ -322,6 +342,95 @@ def serving_leg(n_requests: int, seed: int = 200, budget: int = 1 << 30):
     res["plain_fp32_same_stream"] = {"p50_ms": float(np.percentile(plat, 50)),
                                      "p99_ms": float(np.percentile(plat, 99)), "mean_ms": float(plat.mean())}
     return res
+
+
+def serving_load_workload(n_requests: int, seed: int = 200, budget: int = 1 << 30,
+                          loads=(0.3, 0.5, 0.7, 0.85, 0.95, 1.1)):
+    """Latency against offered load on the serving mix (its scenes, sizes and
+    popularity).  The reference rate is the capacity of the server with every
+    scene resident (fp16 MLP, closed loop: all requests queued at once).
+    Poisson streams at each fraction of it go through that server, through a
+    server whose device budget is 1 GiB (scenes evicted and re-admitted), and
+    through the plain fp32 merf_render on one stream.  Every stream has the
+    same requests in the same order, with the arrival times of one unit-rate
+    Poisson stream scaled to its rate.  The closed-loop capacities of the
+    budgeted server and of the plain path are reported too."""
+    import numpy as np
+    import torch
+    from paper_2302_12249_amd import merf
+
+    scenes, _, sizes, cams, scene_of, rng = _serving_mix(n_requests, seed)
+    arr = merf.camera_array(cams)
+    p16 = merf.render_params(mlp_prec="f16")
+    rays = sum(w * h for (w, h) in sizes)
+    unit = np.cumsum(rng.exponential(1.0, n_requests))
+    outs = [torch.empty((w * h, 4), dtype=torch.float32, device="cuda") for (w, h) in sizes]
+
+    def point(f, lat, last_s):
+        return {"load": f, "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "mean_ms": float(lat.mean()), "completed_Mrays/s": rays / last_s / 1e6}
+
+    def served_curve(srv, ref):
+        """Closed-loop capacity (the last of three passes, so that admissions
+        have settled), then the open-loop streams at fractions of ref (of
+        this capacity if ref is None)."""
+        ids = [srv.add_scene(s) for s in scenes]
+        torch.cuda.synchronize()
+        for _ in range(3):
+            t0 = time.perf_counter()
+            for t in [srv.submit(ids[scene_of[i]], arr, i, outs[i].data_ptr(), p16) for i in range(n_requests)]:
+                srv.wait(t)
+            cap = n_requests / (time.perf_counter() - t0)
+        ref = ref or cap
+        st0 = srv.stats()
+        pts = []
+        for f in loads:
+            waited, last_s = _open_loop_served(srv, ids, scene_of, arr, outs, p16, unit / (f * ref))
+            pts.append(point(f, np.array([w[0] for w in waited]), last_s))
+        st = srv.stats()
+        return ref, cap, {"capacity_req_per_s": cap, "points": pts,
+                          "admissions": int(st["admissions"] - st0["admissions"]),
+                          "evictions": int(st["evictions"] - st0["evictions"])}
+
+    res = {"requests_per_point": n_requests, "hbm_budget": budget, "loads": list(loads)}
+    srv = merf.Server(slots=4, max_batch=16, use_graphs=True)
+    try:
+        ref, _, res["served_all_resident"] = served_curve(srv, None)
+    finally:
+        srv.close()
+    res["reference_req_per_s"] = ref
+    res["reference_Mrays/s"] = rays * ref / n_requests / 1e6
+    srv = merf.Server(slots=4, max_batch=16, use_graphs=True, evict_idle=True, hbm_budget=budget)
+    try:
+        _, _, res["served_budget"] = served_curve(srv, ref)
+    finally:
+        srv.close()
+    rends = [merf.Renderer(s) for s in scenes]
+    try:
+        pf = merf.render_params(order="plain")
+        for i in range(min(8, n_requests)):               # warm up
+            rends[scene_of[i]].render(cams.subset(i), order="plain")
+        torch.cuda.synchronize()
+        back_to_back = _open_loop_plain(rends, arr, scene_of, sizes, np.zeros(n_requests), pf)
+        pts = []
+        for f in loads:
+            arrive = unit / (f * ref)
+            lat = _open_loop_plain(rends, arr, scene_of, sizes, arrive, pf)
+            pts.append(point(f, lat, float((lat + arrive * 1e3).max()) / 1e3))
+    finally:
+        for r in rends:
+            r.close()
+    res["plain_fp32"] = {"capacity_req_per_s": n_requests / (float(back_to_back.max()) / 1e3), "points": pts}
+    at = {p["load"]: p for p in res["served_budget"]["points"]}
+    return {"metric": "p50/p99 frame latency against offered load, served vs plain (serving mix)",
+            "value": at[0.7]["p99_ms"] if 0.7 in at else None,
+            "unit": "ms (p99 of the budgeted server at 0.7 of the resident capacity)",
+            "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+            "config": {"workload": "serving mix: 8 scenes (256^3/1024^2 to 512^3/2048^2, 2-15% occupancy, "
+                                   "1.74 GB), Zipf(1.5) popularity, views of 256^2/512^2/1280x720/1920x1080, "
+                                   "Poisson arrivals at fractions of the served capacity",
+                       "slots": 4, "max_batch": 16, "mlp": "f16 served, f32 plain"},
+            "load_sweep": res}
 
 
 def precision_config(steps: int, scene=None):
@@ -626,9 +735,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["full", "precision", "stress", "variants", "resolutions"], default="full",
+    ap.add_argument("--workload", choices=["full", "precision", "stress", "variants", "resolutions", "serving_load"],
+                    default="full",
                     help="full (default, the headline line), precision (16 x 1080p views), stress, "
-                         "variants (representations: memory against speed) or resolutions (tile order by frame size)")
+                         "variants (representations: memory against speed), resolutions (tile order by frame "
+                         "size) or serving_load (latency against offered load on the serving mix)")
     ap.add_argument("--stress-scenes", type=int, default=32,
                     help="resident scenes of the Stress config (in the default line and --workload stress; 0: skip)")
     ap.add_argument("--precision-steps", type=int, default=5,
@@ -669,6 +780,9 @@ def main():
         return
     if args.workload == "stress":
         print(json.dumps(stress_workload(args.stress_scenes, args.serve_requests)), flush=True)
+        return
+    if args.workload == "serving_load":
+        print(json.dumps(serving_load_workload(max(args.serve_requests, 1))), flush=True)
         return
     scene = synth.preset_scene("full")
     cams = synth.full_camera()
