@@ -509,24 +509,28 @@ void loader_main(merf_server *S) {
                 continue;
             }
             // candidates: resident scenes no request older than `want` needs
-            std::vector<SceneEntry *> cand;
+            // (the queue is in ticket order, so a scene's first waiting
+            // request decides), least requested first
+            std::unordered_map<int32_t, uint64_t> first_wait;
+            for (uint64_t t : S->queue) first_wait.emplace(S->reqs[t].scene, t);
+            struct Cand {
+                double heat;
+                uint64_t last_used;
+                SceneEntry *e;
+            };
+            const auto now = Clock::now();
+            std::vector<Cand> order;
             for (auto &kv : S->scenes) {
                 SceneEntry &e = kv.second;
                 if (e.state != kResident) continue;
-                bool needed = false;
-                for (uint64_t t : S->queue) {
-                    if (t >= want) break;
-                    needed = needed || S->reqs[t].scene == kv.first;
-                }
-                if (!needed) cand.push_back(&e);
+                auto fw = first_wait.find(kv.first);
+                if (fw == first_wait.end() || fw->second > want) order.push_back({heat_at(e, now), e.last_used, &e});
             }
-            const auto now = Clock::now();
-            std::vector<std::pair<double, SceneEntry *>> order;
-            for (SceneEntry *e : cand) order.emplace_back(heat_at(*e, now), e);
-            std::sort(order.begin(), order.end(), [](const auto &a, const auto &b) {
-                return a.first != b.first ? a.first < b.first : a.second->last_used < b.second->last_used;
+            std::sort(order.begin(), order.end(), [](const Cand &a, const Cand &b) {
+                return a.heat != b.heat ? a.heat < b.heat : a.last_used < b.last_used;
             });
-            for (size_t i = 0; i < order.size(); ++i) cand[i] = order[i].second;
+            std::vector<SceneEntry *> cand;
+            for (const Cand &c : order) cand.push_back(c.e);
             size_t room = S->budget - std::min(S->budget, S->resident);
             bool slot_ok = slot >= 0;
             std::vector<SceneEntry *> victims;
