@@ -19,10 +19,11 @@
  *    rendering is first drained: it takes no newer requests until it is
  *    evicted).  Requests older than the waiting one keep being
  *    served, so every request is eventually admitted.  Without evict_idle,
- *    only merf_server_remove_scene frees memory.  After a scene's first
- *    upload, the server's host copy is the device image that upload built
- *    (packed bricks, empty-space grids and all), so a re-admission is a
- *    single host-to-device copy and runs no kernels beside the renders.
+ *    only merf_server_remove_scene frees memory.  With evict_idle, after a
+ *    scene's first upload the server's host copy is the device image that
+ *    upload built (packed bricks, empty-space grids and all), so a
+ *    re-admission is a single host-to-device copy and runs no kernels beside
+ *    the renders.
  *  - Continuous batching: requests queue on the host.  A worker thread owns
  *    `slots` HIP streams.  Whenever a slot is free, it fuses the oldest
  *    request whose scene is resident with the following such requests that

@@ -3,9 +3,9 @@
 // Registered scenes (host copies owned by the server) become resident in
 // device memory under a byte budget: at registration when they fit, otherwise
 // when a request needs them, evicting the least requested scenes that no
-// earlier request needs.  After a scene's first upload its host copy is the
-// device image that upload built, so a re-admission is one copy and runs no
-// kernels beside the renders.  A worker thread continuously batches waiting
+// earlier request needs.  When scenes are evicted, a scene's host copy after
+// its first upload is the device image that upload built, so a re-admission
+// is one copy and runs no kernels beside the renders.  A worker thread continuously batches waiting
 // requests of resident scenes -- any scenes, any image sizes -- into
 // launches of the served render kernel on several HIP streams, with a grid
 // from a fixed set of classes (persistent beyond the largest); a launch reads
@@ -351,8 +351,9 @@ void free_host(SceneEntry &e);
 // one host-to-device copy, which runs on a copy engine: the build kernels
 // (brick packing, empty-space grids) would otherwise run again on every
 // re-admission, beside the renders of the resident scenes, and slow them.
-// Best effort: without host memory for the image, the arrays stay and every
-// admission builds the scene again.
+// Only a server that evicts idle scenes re-admits them, so only such a server
+// keeps images.  Best effort: without host memory for the image, the arrays
+// stay and every admission builds the scene again.
 void keep_image(merf_server *S, SceneEntry &e, merf_scene_t h) {
     const size_t n = e.need;
     void *buf = nullptr;
@@ -386,7 +387,7 @@ int admit(merf_server *S, SceneEntry *se, int slot) {
     const bool from_image = se->imaged;
     int rc = from_image ? scene_from_image_on(se->img, se->host, S->load_stream, &h)
                         : scene_upload_on(&se->desc, S->load_stream, &h);
-    if (rc == MERF_OK && !se->imaged) keep_image(S, *se, h);
+    if (rc == MERF_OK && !se->imaged && S->cfg.evict_idle) keep_image(S, *se, h);   // only evictions re-admit
     if (rc == MERF_OK) rc = write_table(S, slot, h);
     const auto us = std::chrono::duration_cast<std::chrono::microseconds>(Clock::now() - t0).count();
     std::lock_guard<std::mutex> lk(S->mu);
