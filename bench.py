@@ -16,7 +16,11 @@ Prints ONE JSON line.  Besides throughput it reports:
                 on every fifth timed step), against HBM peak;
   latency_ms    p50 / p99 of frames rendered alone (host wall time from the
                 call until the frame is done, prepass included);
-  cpu_baseline  the FP64 oracle on a bounded row sample of the same frame.
+  cpu_baseline  the FP64 oracle on a bounded row sample of the same frame;
+  served        the serving mix through the server (1 GiB budget, and every
+                scene resident) beside plain calls, p50 / p99 latency;
+  serving_load  p50 / p99 latency at fractions of the served capacity;
+  stress        32 resident scenes, 4K and 512^2 requests, served vs plain.
 """
 import argparse
 import hashlib
@@ -746,6 +750,9 @@ def main():
                     help="timed calls per mode of the 16 x 1080p precision config in the default line (0 skips it)")
     ap.add_argument("--serve-requests", type=int, default=240,
                     help="requests in the serving-mix leg (0 skips it)")
+    ap.add_argument("--serve-load", type=int, default=1,
+                    help="1: the default line includes latency against offered load on the serving mix "
+                         "(--serve-requests requests a point); 0 skips it")
     ap.add_argument("--no-overlap", action="store_true",
                     help="skip the two-frames-in-flight leg (its concurrent launches would blur per-kernel profiles)")
     ap.add_argument("--event-every", type=int, default=5,
@@ -957,6 +964,19 @@ def main():
         res["stress"] = {"workload": st["config"]["workload"], "resident_bytes": st["config"]["resident_bytes"],
                          "served_Mrays/s": st["value"], "served": st["served"],
                          "plain_fp32_Mrays/s": st["plain_fp32_Mrays/s"]}
+    if args.serve_requests > 0 and args.serve_load and not args.headline_only:
+        # latency against offered load on the serving mix (p50 / p99 ms from
+        # the scheduled arrival at fractions of the all-resident capacity)
+        sl = serving_load_workload(args.serve_requests, loads=(0.3, 0.5, 0.7, 0.95))["load_sweep"]
+        curve = lambda k: {f'{p["load"]:.2f}': [round(p["p50_ms"], 3), round(p["p99_ms"], 2)]
+                           for p in sl[k]["points"]}
+        res["serving_load"] = {"requests_per_point": sl["requests_per_point"],
+                               "reference_req_per_s": sl["reference_req_per_s"],
+                               "reference_Mrays/s": sl["reference_Mrays/s"],
+                               "p50_p99_ms": {k: curve(k) for k in ("served_all_resident", "served_budget",
+                                                                    "plain_fp32")},
+                               "capacity_req_per_s": {"served_budget": sl["served_budget"]["capacity_req_per_s"],
+                                                      "plain_fp32": sl["plain_fp32"]["capacity_req_per_s"]}}
     images = {"f32": out.cpu().numpy()}
     for name, v in prec.items():
         images[name] = v.pop("_img").cpu().numpy()
