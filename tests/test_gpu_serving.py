@@ -255,6 +255,40 @@ def test_eviction_keeps_the_most_requested_scene(torch, merf, scenes):
         srv.close()
 
 
+def test_readmission_from_device_image_full_size(torch, merf):
+    """Two 256^3 / 1024^2 scenes (three occupancy levels, the empty-space
+    grids of the full-size layout) under a budget that holds one: every
+    re-admission copies the device image kept from the first upload, and
+    every request still gets merf_render's image bit for bit."""
+    say("serving: re-admission from device images, 256^3 / 1024^2 scenes")
+    two = synth.serving_scenes(seeds=(100, 103))
+    sizes = []
+    for sc in two:
+        probe = merf.Server(slots=1)
+        probe.add_scene(sc)
+        sizes.append(probe.stats()["resident_bytes"])
+        probe.close()
+    srv = merf.Server(slots=2, max_batch=2, hbm_budget=max(sizes) + min(sizes) // 2, evict_idle=True)
+    try:
+        ids = [srv.add_scene(sc) for sc in two]
+        order = [0, 1, 0, 1, 1, 0]
+        cams = synth.random_cameras(len(order), seed=29, sizes=[(96, 64), (61, 37)] * 3, inside=1.5)
+        arr = merf.camera_array(cams)
+        outs = [torch.full((int(w) * int(h), 4), float("nan"), device="cuda") for w, h in cams.size]
+        torch.cuda.synchronize()
+        for i, k in enumerate(order):                 # one at a time: each switch evicts the other scene
+            srv.wait(srv.submit(ids[k], arr, i, outs[i].data_ptr(), merf.render_params()))
+        st = srv.stats()
+        say(f"  admissions {st['admissions']} ({st['image_admissions']} from device images), "
+            f"evictions {st['evictions']}")
+        assert st["evictions"] >= 3 and st["image_admissions"] == st["admissions"] - 2
+        for i, k in enumerate(order):
+            alone = render_alone(torch, merf, two[k], cams, i, "f32")
+            assert np.array_equal(outs[i].cpu().numpy(), alone), i
+    finally:
+        srv.close()
+
+
 def test_admission_while_serving_from_threads(torch, merf, scenes):
     """Two client threads keep requesting four scenes, of which two fit: the
     loader must drain and evict scenes that are in use, and every request
