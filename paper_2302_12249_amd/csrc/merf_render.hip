@@ -203,6 +203,11 @@ __device__ __forceinline__ int region_at(float3 o, float3 d, float t) {
 // quarter rate): both factors below 2^24, the low 32 bits of the product.
 __device__ __forceinline__ uint32_t mul24(uint32_t a, uint32_t b) { return __umul24(a, b); }
 
+// Cell of a grid of r cells a side at scaled coordinate v = (p + 2) r / 4,
+// clamped to [0, r - 1] on both sides (one median instruction), so that a
+// lookup stays inside the grid whatever the point.
+__device__ __forceinline__ int cell_index(float v, int r) { return max(min((int)v, r - 1), 0); }
+
 // Byte offset of cell (x, y, z) of an r^3 z-major grid; every factor is
 // below 2^24 (r <= 1024).
 __device__ __forceinline__ uint32_t cell_offset(int x, int y, int z, int r) {
@@ -537,18 +542,25 @@ __device__ __forceinline__ float3 segment_end(float3 o, float3 d, float tb, int 
 }
 
 // Set up the segment of the ray that starts at world parameter ta in region
-// reg: find where the region next changes (Eq. 7 breakpoints), map both ends.
+// reg: find where the region changes (Eq. 7 breakpoints), map both ends.
+// Every region is convex, so the ray leaves reg at the first breakpoint after
+// ta on one of reg's own boundary planes that it crosses outward: inside the
+// cube any face x_j = +-1; in the outer region of axis a (sign s) its face
+// x_a = s when |x_a| shrinks, and a plane x_a = +-x_k when |x_k| grows past
+// |x_a| there.  The direction of a crossing follows from the signs of the
+// direction's components, so it is exact even where several planes meet
+// (a ray through a cube edge crosses the seam between two outer regions into
+// the region it enters, not out of it).  The region entered is read at the
+// midpoint to the next breakpoint of the full set; where that midpoint is
+// within rounding of the exit and still reads reg, it is the region across
+// the exit plane (the outer region of face x_j = +-1, the cube across a face
+// x_a = s, axis k with the sign x_k takes across x_a = +-x_k).
 __device__ __forceinline__ void open_segment(float3 o, float3 d, float ta, int reg, float istep, uint32_t oct_stride,
                                              Segment &s) {
     const Candidates C = make_candidates(o, d);
-    // The region can change only where it is decided: inside the cube when
-    // some |x_j| crosses 1 (candidates 0..5); in the outer region of axis a
-    // when |x_a| crosses 1 or another |x_k| meets |x_a| (candidates 2a, 2a+1
-    // and the pairs with a).  The others are skipped; the next region is
-    // still sampled between consecutive candidates of the full set.
-    // the six relevant candidates: cube {0..5}; axis 0 {0, 1, 6, 7, 8, 9};
+    // the six boundary planes of reg: cube {0..5}; axis 0 {0, 1, 6, 7, 8, 9};
     // axis 1 {2, 3, 6, 7, 10, 11}; axis 2 {4, 5, 8, 9, 10, 11}
-    const int ax = (reg - 1) >> 1;
+    const int ax = (reg - 1) >> 1, neg = (reg - 1) & 1;
     const bool in_cube = reg == 0, a0 = !in_cube && ax == 0, a1 = !in_cube && ax == 1;
     float cr[6];
     cr[0] = in_cube || a0 ? C.c[0] : (a1 ? C.c[2] : C.c[4]);
@@ -557,16 +569,39 @@ __device__ __forceinline__ void open_segment(float3 o, float3 d, float ta, int r
     cr[3] = in_cube ? C.c[3] : (a0 || a1 ? C.c[7] : C.c[9]);
     cr[4] = in_cube ? C.c[4] : (a0 ? C.c[8] : C.c[10]);
     cr[5] = in_cube ? C.c[5] : (a0 ? C.c[9] : C.c[11]);
-    float tb = kInf, cur = ta;
+    // outer regions: the other axes k1 < k2, and for each plane whether
+    // crossing it leaves the region (|x_a| shrinks below 1, or |x_k| grows
+    // past |x_a|)
+    const int k1 = a0 ? 1 : 0, k2 = ax == 2 ? 1 : 2;
+    const float da = ax == 0 ? d.x : (ax == 1 ? d.y : d.z);
+    const float dk1 = k1 == 0 ? d.x : d.y, dk2 = k2 == 1 ? d.y : d.z;
+    const bool sneg = neg != 0;
+    bool out[6];
+    out[0] = in_cube || (!sneg && da < 0.0f);
+    out[1] = in_cube || (sneg && da > 0.0f);
+    out[2] = in_cube || ((dk1 > da) != sneg);
+    out[3] = in_cube || ((da + dk1 < 0.0f) != sneg);
+    out[4] = in_cube || ((dk2 > da) != sneg);
+    out[5] = in_cube || ((da + dk2 < 0.0f) != sneg);
+    float tb = kInf;
+    int hit = 0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        const bool nearer = out[i] && cr[i] > ta && cr[i] < tb;    // ties: the first plane
+        tb = nearer ? cr[i] : tb;
+        hit = nearer ? i : hit;
+    }
+    // the region across the exit plane (regions are 1 + 2k + (x_k < 0)): from
+    // the cube, that of face hit; from axis a, the cube across its faces
+    // (planes 0, 1), axis k across x_a = x_k with the sign of x_a (planes 2, 4)
+    // and across x_a = -x_k with the other sign (planes 3, 5)
+    const int kk = hit < 4 ? k1 : k2;
+    const int across = in_cube ? 1 + hit : (hit < 2 ? 0 : 1 + 2 * kk + (neg ^ (hit & 1)));
     int reg_next = reg;
-    for (int it = 0; it < 13; ++it) {
-        float n1 = next_of<6>(cr, cur);
-        if (!(n1 < kInf)) break;
-        float n2 = next_candidate(C, n1);
-        float tm = n2 < kInf ? 0.5f * (n1 + n2) : 2.0f * n1 + 1.0f;
-        int r2 = region_at(o, d, tm);
-        if (r2 != reg) { tb = n1; reg_next = r2; break; }
-        cur = n1;
+    if (tb < kInf) {
+        const float n2 = next_candidate(C, tb);
+        const int r2 = region_at(o, d, n2 < kInf ? 0.5f * (tb + n2) : 2.0f * tb + 1.0f);
+        reg_next = r2 != reg ? r2 : across;
     }
     s.A = map_region(reg, make_float3(fmaf(ta, d.x, o.x), fmaf(ta, d.y, o.y), fmaf(ta, d.z, o.z)));
     const float3 B = segment_end(o, d, tb, reg);
@@ -604,13 +639,12 @@ __device__ __forceinline__ void open_segment(float3 o, float3 d, float ta, int r
 template <typename S>
 __device__ __forceinline__ int dist_lookup(const S &sc, const Segment &s, float3 p, float &ue) {
     const int r = sc.dist_res;
-    // cell of p: (p + 2) r / 4 rounded down; contracted points have p >= -2
-    // up to rounding, so truncation equals the floor and no lower clamp is
-    // needed
+    // cell of p: (p + 2) r / 4 rounded down (contracted points have p >= -2
+    // up to rounding, so truncation is the floor), clamped to the grid
     const float os = sc.dist_scale, os2 = sc.dist_off;
-    const int qx = min((int)fmaf(p.x, os, os2), r - 1);
-    const int qy = min((int)fmaf(p.y, os, os2), r - 1);
-    const int qz = min((int)fmaf(p.z, os, os2), r - 1);
+    const int qx = cell_index(fmaf(p.x, os, os2), r);
+    const int qy = cell_index(fmaf(p.y, os, os2), r);
+    const int qz = cell_index(fmaf(p.z, os, os2), r);
     const int D = load_at<uint8_t>(sc.dist, s.doff + cell_offset(qx, qy, qz, r));
     const int ext = D > 0 ? D - 1 : 0;
     const float h = sc.dist_cell;
@@ -994,9 +1028,9 @@ __device__ __forceinline__ void render_tile(const S &sc, const Cam &cam, int lt,
                     if (l < sc.occ_levels && empty < 0 && !(um < known[l])) {
                         const int rl = sc.occ_res[l];
                         const float os = (float)rl * 0.25f, os2 = 2.0f * os;
-                        const int qx = min((int)fmaf(p.x, os, os2), rl - 1);
-                        const int qy = min((int)fmaf(p.y, os, os2), rl - 1);
-                        const int qz = min((int)fmaf(p.z, os, os2), rl - 1);
+                        const int qx = cell_index(fmaf(p.x, os, os2), rl);
+                        const int qy = cell_index(fmaf(p.y, os, os2), rl);
+                        const int qz = cell_index(fmaf(p.z, os, os2), rl);
                         if (kStats) ++cnt.occ_lookups;
                         const bool occ = load_at<uint8_t>(sc.occ[l], cell_offset(qx, qy, qz, rl)) != 0;
                         // exit parameter of this cell along the segment (slab test)

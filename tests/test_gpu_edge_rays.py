@@ -62,3 +62,20 @@ def test_edge_rays_skip_modes_and_orders_agree(torch, merf, scene):
     c = gpu_render(torch, merf, scene, cams, order="plain")
     assert np.array_equal(a, b)
     assert np.array_equal(a, c)
+
+
+def test_breakpoints_within_rounding_of_each_other(torch, merf):
+    """A ray whose cube exit (face y = -1) and a plane crossing of no concern
+    to the region it enters (x = -z) lie 1.7e-7 apart in t: the region entered
+    must still be the outer region of -y, so the ray's samples stay in the
+    contracted domain (a float32 replay of the segment search found this ray,
+    pixel (1599, 473) of this camera, among five 1080p cameras).  Row 473 of
+    the tiny scene from that camera against the oracle."""
+    from gpu_helpers import rows_of
+    scene = synth.preset_scene("tiny")
+    cams = synth.full_camera(seed=0)
+    say("tiny scene, full_camera(seed=0) 1920x1080: the row of a ray with near-coincident breakpoints")
+    gpu = gpu_render(torch, merf, scene, cams)
+    ref, st = oracle.render(scene, cams, rows_stride=1080, row_offset=473)
+    check(gpu[rows_of(cams, 1080, 473)], ref, st["fragile"], "tiny seed-0 row 473")
+    assert st["fragile"][1599] == 0
