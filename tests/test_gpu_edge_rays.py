@@ -79,3 +79,16 @@ def test_breakpoints_within_rounding_of_each_other(torch, merf):
     ref, st = oracle.render(scene, cams, rows_stride=1080, row_offset=473)
     check(gpu[rows_of(cams, 1080, 473)], ref, st["fragile"], "tiny seed-0 row 473")
     assert st["fragile"][1599] == 0
+
+
+def test_many_inside_views_sampled_rows(torch, merf):
+    """Eight more views from inside the cube (full_camera seeds 0-7 at
+    640x360, every ray leaving the cube into the outer regions) on the tiny
+    scene, every 45th row against the oracle."""
+    from gpu_helpers import rows_of
+    scene = synth.preset_scene("tiny")
+    cams = synth.concat_cameras([synth.full_camera(seed=s, w=640, h=360) for s in range(8)])
+    say("tiny scene, eight inside views at 640x360, every 45th row")
+    gpu = gpu_render(torch, merf, scene, cams)
+    ref, st = oracle.render(scene, cams, rows_stride=45, row_offset=22)
+    check(gpu[rows_of(cams, 45, 22)], ref, st["fragile"], "tiny eight inside views")
